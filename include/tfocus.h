@@ -1,0 +1,217 @@
+/*
+ * tfocus.h -- C ABI of libtfocus, an MI355X (gfx950) implementation of the
+ * tight-focusing method of Panova et al., "Optimized computation of tight
+ * focusing of short pulses using mapping to periodic space"
+ * (arXiv:2010.00409).
+ *
+ * The calls follow the paper's problem statement: put a pulse on the
+ * focusing sphere and map it into a periodic layer (Sec. II.B-II.C), advance
+ * it with the dispersion-free spectral step (Sec. II.A), and read the focal
+ * field back through the cut-out (Sec. II.C, Eqs. (14)-(16)).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Units: c = 1.  Lengths are in any unit; the natural one is the central
+ *   wavelength.  Time is length / c.  Fields are in the CGS form of the paper
+ *   (E and B share units).
+ * Field layout: one contiguous array [6][nz][ny][nx] of the solver's element
+ *   type (float for TF_F32, double for TF_F64), components Ex, Ey, Ez, Bx, By,
+ *   Bz, x fastest.  Node (i, j, k) sits at (x_min + i dx, y_min + j dy,
+ *   z_min + k dz); the grid is periodic on all three axes.
+ * Memory: pointers flagged "on_device" are HIP device pointers on the
+ *   solver's device (for example a torch tensor's data_ptr()); others are
+ *   host pointers.  Caller buffers are borrowed only for the call and, for
+ *   device pointers, until the work queued on the solver's stream completes.
+ *   Objects own all memory they allocate.
+ * Streams: all device work is queued on the stream given at creation (NULL
+ *   means the null stream).  Only calls that return data into host memory
+ *   synchronise that stream.
+ * Errors: every call returns a tf_status; no exception crosses the ABI.
+ *   Arguments are validated before any HIP call.  tf_last_error() returns a
+ *   message for the last failure on the calling thread.
+ * Threading: one object per thread; distinct objects are independent.
+ */
+#ifndef TFOCUS_H
+#define TFOCUS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TF_OK = 0,
+    TF_EINVAL = -1,        /* null pointer, bad size or bad parameter        */
+    TF_EUNSUPPORTED = -2,  /* axis length with a prime factor other than 2,3 */
+    TF_ENOMEM = -3,        /* device allocation failed or exceeds the cap    */
+    TF_EDEVICE = -4,       /* a HIP call failed (message has the HIP error)  */
+    TF_ESTATE = -5,        /* call not valid in the object's current state   */
+    TF_EDOMAIN = -6,       /* period D = nx dx not larger than the pulse L   */
+    TF_ENONFINITE = -7     /* non-finite value found by a checked call       */
+} tf_status;
+
+typedef enum { TF_F32 = 0, TF_F64 = 1 } tf_precision;
+
+/* Longitudinal profile u_l of the pulse. */
+typedef enum {
+    TF_ENV_COS2 = 0,      /* sin(2 pi z/lambda - cep) cos^2(pi z/L), Eq. (7)      */
+    TF_ENV_GAUSS = 1,     /* sin(2 pi z/lambda - cep) exp(-z^2 ln4/(n lambda)^2),
+                             Sec. III.B.1, cut to |z| <= L/2                     */
+    TF_ENV_SPECTRAL = 2   /* Re sum_m a_m exp(i(phi_m - w_m z)), Gaussian spectrum
+                             of relative width `bandwidth`, spectral phase
+                             cep + pi/2 + gdd (w-w0)^2/2 + tod (w-w0)^3/6 over
+                             nfreq samples, max |g| = 1, cut to |z| <= L/2      */
+} tf_envelope;
+
+/* Transverse profile u_ts(alpha), alpha = angle from the -x axis. */
+typedef enum {
+    TF_TS_FLATTOP = 0,    /* Eq. (5): 1 below theta - eps/2, cos^2 edge, 0 above */
+    TF_TS_GAUSS = 1       /* exp(-alpha^2/theta^2) for alpha <= pi/2, Sec. III.B.1 */
+} tf_transverse;
+
+typedef enum {
+    TF_POL_LINEAR = 0,    /* d = (0, cos pol_angle, sin pol_angle); with
+                             ellipticity e a second part along (0,-sin,cos) in
+                             quadrature, amplitudes 1/sqrt(1+e^2), e/sqrt(1+e^2) */
+    TF_POL_RADIAL = 1     /* d = x (along the optical axis)                      */
+} tf_polarization;
+
+/* Periodic grid; the layer period along x is D = nx * dx. */
+typedef struct {
+    int32_t nx, ny, nz;   /* nx even; each length a product of 2s and 3s,
+                             8 <= n <= 1024 (tf_supported_length)               */
+    int32_t reserved;
+    double dx, dy, dz;    /* > 0                                                 */
+    double x_min, y_min, z_min;
+} tf_grid;
+
+/* Pulse on the focusing sphere, Sec. II.B (flat-top) and Sec. III.B.1
+ * (Gaussian beam).  E = u s0, B = u s1 with u(R) = (A/R) u_l(R - R0)
+ * u_ts(alpha), s1 = d x R / |d x R|, s0 = R x (d x R) / |R x (d x R)|. */
+typedef struct {
+    int32_t envelope;      /* tf_envelope                                        */
+    int32_t transverse;    /* tf_transverse                                      */
+    int32_t polarization;  /* tf_polarization                                    */
+    int32_t nfreq;         /* spectral samples (TF_ENV_SPECTRAL), 1..4096         */
+    double wavelength;     /* central wavelength lambda > 0                      */
+    double R0;             /* radius of the pulse centre                         */
+    double L;              /* full support length; R_min,max = R0 -/+ L/2        */
+    double ncycles;        /* TF_ENV_GAUSS: intensity FWHM in wavelengths        */
+    double f_number;       /* theta = arctan(1/(2 f)) when theta <= 0            */
+    double theta;          /* opening half-angle (> 0 overrides f_number)        */
+    double eps;            /* flat-top edge width                                 */
+    double P0;             /* cycle-averaged power through the cap, Eq. (9)       */
+    double pol_angle, ellipticity;
+    double cep, gdd, tod;  /* carrier-envelope phase, chirp (time units^2, ^3)   */
+    double bandwidth;      /* TF_ENV_SPECTRAL: relative 1/e half-width delta      */
+} tf_pulse;
+
+/* Geometry derived from a pulse by tf_pulse_geometry / tf_set_pulse. */
+typedef struct {
+    double theta;          /* opening angle, Sec. II.B                            */
+    double A;              /* amplitude, Eq. (9) (flat-top) or sqrt(4P0/F(theta)) */
+    double R_min, R_max;   /* R0 -/+ L/2                                           */
+    double L;
+    double D_min;          /* Eq. (12) at theta                                    */
+    double alpha_max;      /* angular support edge                                 */
+    double D;              /* nx dx of the solver (tf_set_pulse only)              */
+    int32_t overlap;       /* D < D_min: replicas overlap (allowed, Sec. II.C)     */
+    int32_t reserved;
+} tf_pulse_info;
+
+/* Node-aligned focal window of wx*wy*wz nodes centred on the node nearest
+ * (cx, cy, cz); node i along x is centre + i - wx/2.  x wraps (mapping T,
+ * Eq. (13)); y and z must stay inside the grid. */
+typedef struct {
+    int32_t wx, wy, wz, reserved;
+    double cx, cy, cz;
+} tf_window;
+
+typedef struct tf_solver tf_solver;
+
+/* Version string "tfocus <major>.<minor>". */
+const char* tf_version(void);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char* tf_last_error(void);
+
+/* 1 if n is a supported axis length (product of 2s and 3s in [8, 1024]). */
+int32_t tf_supported_length(int32_t n);
+
+/* Host only.  Opening angle (Sec. II.B), amplitude (Eq. (9); Gaussian
+ * transverse: sqrt(4 P0 / F(theta)), F of Sec. III.B.1), radii and D_min
+ * (Eq. (12)).  info->D and info->overlap are set to 0. */
+tf_status tf_pulse_geometry(const tf_pulse* pulse, tf_pulse_info* info);
+
+/* Host only.  The periodic layer of Sec. II.C for a pulse: D = nx dx,
+ * x_min = -R_min - D moved onto the node grid so the origin is a node,
+ * y_min = -(ny/2) dy, z_min = -(nz/2) dz.  Writes *out. */
+tf_status tf_layer_grid(const tf_pulse* pulse, int32_t nx, int32_t ny, int32_t nz,
+                        double dx, double dy, double dz, tf_grid* out);
+
+/* Create a solver on the current HIP device.  Allocates the field state
+ * (6 nx ny nz elements) and the half spectrum (6 nz ny nkx complex, nkx =
+ * nx/2 + 1 rounded up to 4).  The state starts at zero with t = 0.
+ * hip_stream: hipStream_t or NULL.  TF_ENOMEM if the environment variable
+ * TFOCUS_MAX_DEVICE_BYTES is set below the bytes needed. */
+tf_status tf_create(const tf_grid* grid, int32_t precision, void* hip_stream,
+                    tf_solver** out);
+
+/* Free everything the solver owns (waits for its stream). NULL is a no-op. */
+tf_status tf_destroy(tf_solver* s);
+
+/* Copy a state [6][nz][ny][nx] in, set the time to t.  The state is taken as
+ * is (no projection).  Host sources are copied synchronously. */
+tf_status tf_set_fields(tf_solver* s, const void* src, int32_t src_on_device, double t);
+
+/* Copy the state out.  A host destination synchronises the stream. */
+tf_status tf_get_fields(tf_solver* s, void* dst, int32_t dst_on_device);
+
+/* Borrowed device pointer to the state array (valid until tf_destroy). */
+tf_status tf_state_ptr(tf_solver* s, void** dev_ptr);
+
+/* Initialise E and B from the pulse, Eqs. (5)-(11), mapped into the layer:
+ * every node sums the pulse over its preimages x + n D (Eq. (13) and the
+ * superposition remark after Eq. (12)).  Sets t = 0 and the cut-out radii,
+ * and makes the next tf_advance remove the longitudinal part of B once
+ * (E loses its longitudinal part at every step, Eq. (3)).
+ * TF_EDOMAIN if D = nx dx <= L.  info (nullable) receives the geometry. */
+tf_status tf_set_pulse(tf_solver* s, const tf_pulse* pulse, tf_pulse_info* info);
+
+/* Cut-out radii R_min, R_max for tf_read_focal when the state was loaded
+ * with tf_set_fields. */
+tf_status tf_set_cutout(tf_solver* s, double R_min, double R_max);
+
+/* Advance nsteps steps of dt (any sign and size; one step of any length is
+ * exact, Sec. II.A).  Each step: forward 3-D real FFT of the six components,
+ * per-mode rotation of Eqs. (3)-(4) with C = cos(c|k|dt), S = sin(c|k|dt),
+ * inverse FFT.  k-space conventions: forward transform exp(-i k.x); k_hat =
+ * 0 at k = 0; Nyquist indices contribute 0 to k.  t += nsteps * dt.
+ * Asynchronous on the solver's stream. */
+tf_status tf_advance(tf_solver* s, int64_t nsteps, double dt);
+
+/* Focal window [6][wz][wy][wx] at the current time: u(R) = u~(T(R)) I_S(t)(R),
+ * Eqs. (14)-(16), with the third case of Eq. (15) read as "x >= 0 and
+ * R > r(t)".  dst holds 6 wx wy wz elements of the solver's type.
+ * TF_ESTATE if no cut-out radii are known; TF_EINVAL if the window leaves
+ * the grid transversely. */
+tf_status tf_read_focal(tf_solver* s, const tf_window* win, void* dst, int32_t dst_on_device);
+
+/* Synchronous diagnostics of the current state: energy = sum over nodes of
+ * E^2 + B^2; max_div_e = max |k_hat . E_hat| / max |E_hat| over modes and
+ * likewise for B.  Any pointer may be NULL.  TF_ENONFINITE if the energy is
+ * not finite. */
+tf_status tf_diagnostics(tf_solver* s, double* energy, double* max_div_e, double* max_div_b);
+
+/* Current time t (host bookkeeping, no synchronisation). */
+tf_status tf_time(const tf_solver* s, double* t);
+
+/* Grid the solver was created with. */
+tf_status tf_get_grid(const tf_solver* s, tf_grid* grid);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TFOCUS_H */

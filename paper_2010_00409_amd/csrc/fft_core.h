@@ -1,0 +1,168 @@
+// Device building blocks of the spectral step: complex arithmetic, radix
+// 2/3/4/8 butterflies and a Stockham autosort FFT over sequences held in LDS.
+//
+// Transform convention (the forward transform of the spectral solver,
+// Sec. II.A): X[m] = sum_j x[j] w^(m j) with w = exp(DIR 2 pi i / N),
+// DIR = -1 forward, +1 inverse (unnormalised).  Twiddles come from a table
+// tw[e] = exp(-2 pi i e / N), e in [0, N), built on the host in float64 from
+// the exact integer phase and rounded to the element type.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace tf {
+
+template <typename T> struct cplx_of;
+template <> struct cplx_of<float> { using type = float2; };
+template <> struct cplx_of<double> { using type = double2; };
+template <typename T> using C2 = typename cplx_of<T>::type;
+
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { a.x += b.x; a.y += b.y; return a; }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { a.x -= b.x; a.y -= b.y; return a; }
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+    V r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+}
+template <typename V> __device__ __forceinline__ V cconj(V a) { a.y = -a.y; return a; }
+// a * (DIR i): DIR = +1 -> (-y, x); DIR = -1 -> (y, -x)
+template <int DIR, typename V> __device__ __forceinline__ V cmul_i(V a) {
+    V r;
+    if (DIR > 0) { r.x = -a.y; r.y = a.x; } else { r.x = a.y; r.y = -a.x; }
+    return r;
+}
+template <typename V, typename S> __device__ __forceinline__ V cscale(V a, S s) { a.x *= s; a.y *= s; return a; }
+
+template <typename T> struct Consts;
+template <> struct Consts<float> {
+    static constexpr float r2 = 0.70710678118654752440f;   // sqrt(2)/2
+    static constexpr float r3 = 0.86602540378443864676f;   // sqrt(3)/2
+};
+template <> struct Consts<double> {
+    static constexpr double r2 = 0.70710678118654752440;
+    static constexpr double r3 = 0.86602540378443864676;
+};
+
+// In-register DFTs of length R; output in natural order v[0..R).
+template <typename T, int DIR> __device__ __forceinline__ void dft2(C2<T>* v) {
+    C2<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b); v[1] = csub(a, b);
+}
+
+template <typename T, int DIR> __device__ __forceinline__ void dft3(C2<T>* v) {
+    C2<T> s = cadd(v[1], v[2]);
+    C2<T> d = csub(v[1], v[2]);
+    C2<T> m = csub(v[0], cscale(s, T(0.5)));
+    C2<T> t = cscale(cmul_i<DIR>(d), Consts<T>::r3);
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(m, t);
+    v[2] = csub(m, t);
+}
+
+template <typename T, int DIR> __device__ __forceinline__ void dft4(C2<T>* v) {
+    C2<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    C2<T> t2 = cadd(v[1], v[3]), t3 = cmul_i<DIR>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2); v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3); v[3] = csub(t1, t3);
+}
+
+template <typename T, int DIR> __device__ __forceinline__ void dft8(C2<T>* v) {
+    C2<T> b[4], c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { b[k] = cadd(v[k], v[k + 4]); c[k] = csub(v[k], v[k + 4]); }
+    // c_k *= w8^k, w8 = exp(DIR 2 pi i / 8)
+    const T s = Consts<T>::r2;
+    { C2<T> d = c[1]; C2<T> id = cmul_i<DIR>(d); c[1].x = s * (d.x + id.x); c[1].y = s * (d.y + id.y); }
+    c[2] = cmul_i<DIR>(c[2]);
+    { C2<T> d = c[3]; C2<T> id = cmul_i<DIR>(d); c[3].x = s * (id.x - d.x); c[3].y = s * (id.y - d.y); }
+    dft4<T, DIR>(b);
+    dft4<T, DIR>(c);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) { v[2 * m] = b[m]; v[2 * m + 1] = c[m]; }
+}
+
+template <typename T, int R, int DIR> __device__ __forceinline__ void dftR(C2<T>* v) {
+    if constexpr (R == 2) dft2<T, DIR>(v);
+    else if constexpr (R == 3) dft3<T, DIR>(v);
+    else if constexpr (R == 4) dft4<T, DIR>(v);
+    else dft8<T, DIR>(v);
+}
+
+// Radix schedule of a length N = 2^a 3^b: radix-8 stages, then one radix-4
+// or radix-2 stage for the rest of the power of two, then radix-3 stages.
+constexpr int log2_part(int n) { int a = 0; while (n % 2 == 0) { n /= 2; ++a; } return a; }
+constexpr int log3_part(int n) { int b = 0; while (n % 3 == 0) { n /= 3; ++b; } return b; }
+template <int N> struct Plan {
+    static constexpr int a = log2_part(N);
+    static constexpr int b = log3_part(N);
+    static constexpr int n8 = a / 3;
+    static constexpr int rem = a % 3;
+    static constexpr int nst = n8 + (rem ? 1 : 0) + b;
+    static constexpr int radix(int s) { return s < n8 ? 8 : ((rem && s == n8) ? (1 << rem) : 3); }
+    static_assert(N == (1 << a) * (b == 0 ? 1 : (b == 1 ? 3 : (b == 2 ? 9 : 27))), "N must be 2^a 3^b");
+};
+
+// LDS placement of element n of sequence s: one pad slot every 32 elements
+// breaks the power-of-two strides of the Stockham write pattern.
+template <int N> struct Lds {
+    static constexpr int P = N + N / 32 + 1;           // sequence pitch
+    __device__ __forceinline__ static int at(int s, int n) { return s * P + n + (n >> 5); }
+};
+
+// One Stockham stage over NSEQ sequences of length N in LDS, in place:
+// task (s, j), j < N/R, reads x[j + r N/R], applies w^(r (j mod NS)) with
+// w = exp(DIR 2 pi i / (NS R)), does a length-R DFT, and writes
+// y[(j / NS) NS R + (j mod NS) + r NS].
+template <typename T, int N, int R, int NS, int NSEQ, int NT, int DIR>
+__device__ __forceinline__ void stockham_stage(C2<T>* buf, const C2<T>* tw, int tid) {
+    constexpr int M = N / R;
+    constexpr int TASKS = NSEQ * M;
+    constexpr int TPT = (TASKS + NT - 1) / NT;
+    C2<T> v[TPT][R];
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+        const int task = tid + q * NT;
+        if (TASKS % NT == 0 || task < TASKS) {
+            const int s = task / M, j = task % M;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = buf[Lds<N>::at(s, j + r * M)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+        const int task = tid + q * NT;
+        if (TASKS % NT == 0 || task < TASKS) {
+            const int s = task / M, j = task % M;
+            const int jm = j % NS;
+            if constexpr (NS > 1) {
+                constexpr int STEP = N / (NS * R);
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    C2<T> w = tw[r * jm * STEP];
+                    if (DIR > 0) w = cconj(w);
+                    v[q][r] = cmul(v[q][r], w);
+                }
+            }
+            dftR<T, R, DIR>(v[q]);
+            const int base = (j / NS) * NS * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[Lds<N>::at(s, base + r * NS)] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int N, int NSEQ, int NT, int DIR, int S = 0, int NS = 1>
+__device__ __forceinline__ void fft_lds(C2<T>* buf, const C2<T>* tw, int tid) {
+    if constexpr (S < Plan<N>::nst) {
+        constexpr int R = Plan<N>::radix(S);
+        stockham_stage<T, N, R, NS, NSEQ, NT, DIR>(buf, tw, tid);
+        fft_lds<T, N, NSEQ, NT, DIR, S + 1, NS * R>(buf, tw, tid);
+    }
+}
+
+// Copy a twiddle table of N entries into LDS (caller synchronises).
+template <typename T, int N, int NT>
+__device__ __forceinline__ void load_twiddles(C2<T>* dst, const C2<T>* __restrict__ src, int tid) {
+    for (int e = tid; e < N; e += NT) dst[e] = src[e];
+}
+
+}  // namespace tf

@@ -1,0 +1,21 @@
+// Pass kernels instantiated for float elements.
+#include "fft_passes.inc"
+
+namespace tf {
+template hipError_t launch_x_forward<float>(const float*, void*, const void*, int, int, int, hipStream_t);
+template hipError_t launch_x_inverse<float>(const void*, float*, const void*, int, int, int, hipStream_t);
+template hipError_t launch_y_pass<float>(void*, const void*, int, int, int, int, hipStream_t);
+template hipError_t launch_z_pass<float>(void*, const void*, const StepParams&, int, double*, int*, hipStream_t);
+template int z_pass_blocks<float>(int, int, int);
+}  // namespace tf
+
+namespace tf {
+bool fft_length_supported(int n) {
+    switch (n) {
+#define X(m) case m: return true;
+        TF_FOR_LENGTHS(X)
+#undef X
+    }
+    return false;
+}
+}  // namespace tf

@@ -1,0 +1,75 @@
+// Internal interface between the host engine and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace tf {
+
+// Spectral layout: S[kz][ky][kx][c], kx in [0, nkx) with nkx = nx/2 + 1
+// rounded up to a multiple of 4 (slots beyond nx/2 are held at zero), c the
+// six field components; one mode's six components are contiguous.
+inline int nkx_of(int nx) { return ((nx / 2 + 1) + 3) / 4 * 4; }
+
+struct StepParams {
+    int nx, ny, nz, nkx;
+    double kfx, kfy, kfz;    // 2 pi / (n d) per axis
+    double cdt;              // c dt
+    double scale;            // 1 / (nx ny nz)
+    int project_b;           // also remove the longitudinal part of B
+};
+
+enum ZMode { Z_STEP = 0, Z_DIAG = 1 };
+
+// Forward x pass: real state [6][nz][ny][nx] -> spectral (x transformed).
+template <typename T> hipError_t launch_x_forward(const T* real, void* spec, const void* tw,
+                                                  int nx, int ny, int nz, hipStream_t st);
+// Inverse x pass: spectral -> real state.
+template <typename T> hipError_t launch_x_inverse(const void* spec, T* real, const void* tw,
+                                                  int nx, int ny, int nz, hipStream_t st);
+// In-place y transform of the spectral array, dir = -1 forward, +1 inverse.
+template <typename T> hipError_t launch_y_pass(void* spec, const void* tw, int nx, int ny, int nz,
+                                               int dir, hipStream_t st);
+// z pass: Z_STEP = forward z FFT, Eqs. (3)-(4) update, inverse z FFT, in place;
+// Z_DIAG = forward z FFT and per-block maxima |k.E|, |k.B|, |E|, |B| into
+// partials (4 doubles per block), no store.  Returns the block count in *nblocks.
+template <typename T> hipError_t launch_z_pass(void* spec, const void* tw, const StepParams& p,
+                                               int mode, double* partials, int* nblocks,
+                                               hipStream_t st);
+template <typename T> int z_pass_blocks(int nx, int ny, int nz);
+
+// Twiddle tables are per axis length: tw[e] = exp(-2 pi i e / n).
+bool fft_length_supported(int n);
+
+// ---- field kernels (init + map, cut-out, reductions) ----
+
+struct PulseDev {
+    int envelope, transverse, polarization, nfreq;
+    double lambda, R0, L, ncycles, theta, eps, A, alpha_max, cep;
+    double gnorm;                 // spectral normalisation
+    int nparts;                   // 1 or 2 polarisation parts
+    double amp[2], d[2][3], phase_off[2];
+    const double* spec;           // nfreq x {w, a, phi} (spectral only)
+};
+
+struct GridDev {
+    int nx, ny, nz;
+    double dx, dy, dz, x_min, y_min, z_min;
+};
+
+template <typename T> hipError_t launch_init_map(T* state, const GridDev& g, const PulseDev& p,
+                                                 hipStream_t st);
+template <typename T> hipError_t launch_readout(const T* state, T* out, const GridDev& g,
+                                                int wx, int wy, int wz, long ic, long jc, long kc,
+                                                double t, double R_min, double R_max,
+                                                hipStream_t st);
+// Sum of squares of n elements into partials[nb] (fixed grid, deterministic).
+template <typename T> hipError_t launch_sumsq(const T* x, size_t n, double* partials, int nb,
+                                              hipStream_t st);
+// Single-block reductions of m partials: op 0 = sum, 1 = max; stride/offset
+// select a strided slice (for the 4-wide z-diagnostic partials).
+hipError_t launch_reduce(const double* partials, int m, int stride, int offset, int op,
+                         double* out, hipStream_t st);
+
+constexpr int SUMSQ_BLOCKS = 1024;
+
+}  // namespace tf

@@ -1,0 +1,552 @@
+// Host engine behind the C ABI of include/tfocus.h: argument validation,
+// pulse geometry, twiddle tables, buffers and the step driver.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tfocus.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tf_status fail(tf_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+#define TF_HIP(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(TF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));       \
+    } while (0)
+
+bool length_ok(int n) {
+    if (n < 8 || n > 1024) return false;
+    int m = n;
+    while (m % 2 == 0) m /= 2;
+    while (m % 3 == 0) m /= 3;
+    return m == 1 && tf::fft_length_supported(n);
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// ---- pulse geometry (host, float64) ----
+
+// F(theta0) = int_0^pi sin(a) exp(-2 a^2 / theta0^2) da by composite Simpson
+// on [0, min(pi, 12 theta0)] (the integrand is below e^-288 beyond).
+double F_gauss(double t0) {
+    const double b = std::fmin(M_PI, 12.0 * t0);
+    const int n = 1 << 20;
+    const double h = b / n;
+    auto f = [&](double a) { return std::sin(a) * std::exp(-2.0 * a * a / (t0 * t0)); };
+    double s = f(0.0) + f(b);
+    for (int i = 1; i < n; ++i) s += (i & 1 ? 4.0 : 2.0) * f(i * h);
+    return s * h / 3.0;
+}
+
+tf_status validate_pulse(const tf_pulse* p) {
+    if (!p) return fail(TF_EINVAL, "pulse is NULL");
+    if (p->envelope < 0 || p->envelope > 2) return fail(TF_EINVAL, "unknown envelope");
+    if (p->transverse < 0 || p->transverse > 1) return fail(TF_EINVAL, "unknown transverse profile");
+    if (p->polarization < 0 || p->polarization > 1) return fail(TF_EINVAL, "unknown polarization");
+    if (!finite_pos(p->wavelength)) return fail(TF_EINVAL, "wavelength must be > 0");
+    if (!finite_pos(p->L)) return fail(TF_EINVAL, "L must be > 0");
+    if (!finite_pos(p->R0) || !(p->R0 - 0.5 * p->L > 0.0)) return fail(TF_EINVAL, "need R0 > L/2 > 0");
+    if (!(p->theta > 0.0) && !finite_pos(p->f_number)) return fail(TF_EINVAL, "need theta > 0 or f_number > 0");
+    if (p->theta > 0.0 && !(p->theta < M_PI)) return fail(TF_EINVAL, "theta must be < pi");
+    if (p->transverse == TF_TS_FLATTOP && !finite_pos(p->eps)) return fail(TF_EINVAL, "eps must be > 0");
+    if (!std::isfinite(p->P0) || p->P0 < 0.0) return fail(TF_EINVAL, "P0 must be >= 0");
+    if (p->envelope == TF_ENV_GAUSS && !finite_pos(p->ncycles)) return fail(TF_EINVAL, "ncycles must be > 0");
+    if (p->envelope == TF_ENV_SPECTRAL) {
+        if (p->nfreq < 1 || p->nfreq > 4096) return fail(TF_EINVAL, "nfreq must be in [1, 4096]");
+        if (!finite_pos(p->bandwidth)) return fail(TF_EINVAL, "bandwidth must be > 0");
+        if (!std::isfinite(p->gdd) || !std::isfinite(p->tod)) return fail(TF_EINVAL, "chirp must be finite");
+    }
+    if (!std::isfinite(p->cep) || !std::isfinite(p->pol_angle) || !std::isfinite(p->ellipticity))
+        return fail(TF_EINVAL, "phase/polarisation parameters must be finite");
+    if (p->polarization == TF_POL_RADIAL && p->ellipticity != 0.0)
+        return fail(TF_EINVAL, "radial polarisation takes no ellipticity");
+    return TF_OK;
+}
+
+double theta_of(const tf_pulse* p) {
+    return p->theta > 0.0 ? p->theta : std::atan(1.0 / (2.0 * p->f_number));
+}
+
+void geometry(const tf_pulse* p, tf_pulse_info* g) {
+    std::memset(g, 0, sizeof(*g));
+    const double th = theta_of(p);
+    g->theta = th;
+    g->L = p->L;
+    g->R_min = p->R0 - 0.5 * p->L;
+    g->R_max = p->R0 + 0.5 * p->L;
+    if (p->transverse == TF_TS_FLATTOP) {
+        g->A = std::sqrt(4.0 * p->P0 / (1.0 - std::cos(th)));
+        g->alpha_max = th + 0.5 * p->eps;
+    } else {
+        g->A = std::sqrt(4.0 * p->P0 / F_gauss(th));
+        g->alpha_max = 0.5 * M_PI;
+    }
+    const double s = std::sin(th);
+    g->D_min = -g->R_min * std::cos(th) + std::sqrt(g->R_max * g->R_max - g->R_min * g->R_min * s * s);
+}
+
+// Spectral samples {w, a, phi} of the sampled Gaussian spectrum and the
+// normalisation max |g| over zeta_j = j lambda / 128 inside the window.
+void spectral_table(const tf_pulse* p, std::vector<double>& tab, double& gnorm) {
+    const int M = p->nfreq;
+    const double w0 = 2.0 * M_PI / p->wavelength;
+    const double dl = p->bandwidth;
+    const double X = 4.0;
+    tab.clear();
+    for (int m = 0; m < M; ++m) {
+        const double x = -X + (m + 0.5) * (2.0 * X / M);
+        const double w = w0 * (1.0 + dl * x);
+        if (!(w > 0.0)) continue;
+        const double u = (w - w0) / (dl * w0), v = (w + w0) / (dl * w0);
+        const double a = std::exp(-(u * u)) - std::exp(-(v * v));
+        const double dw = w - w0;
+        const double phi = p->gdd * dw * dw / 2.0 + p->tod * dw * dw * dw / 6.0;
+        tab.push_back(w);
+        tab.push_back(a);
+        tab.push_back(phi);
+    }
+    const double h = p->wavelength / 128.0;
+    const long jmax = (long)std::floor(0.5 * p->L / h);
+    gnorm = 0.0;
+    const int K = (int)(tab.size() / 3);
+    for (long j = -jmax; j <= jmax; ++j) {
+        const double z = j * h;
+        double acc = 0.0;
+        for (int m = 0; m < K; ++m) acc += tab[3 * m + 1] * std::cos(p->cep + 0.5 * M_PI + tab[3 * m + 2] - tab[3 * m] * z);
+        gnorm = std::fmax(gnorm, std::fabs(acc));
+    }
+}
+
+std::vector<double> twiddle_table(int n) {
+    std::vector<double> t(2 * n);
+    for (int e = 0; e < n; ++e) {
+        const double a = 2.0 * M_PI * (double)e / (double)n;
+        t[2 * e] = std::cos(a);
+        t[2 * e + 1] = -std::sin(a);
+    }
+    return t;
+}
+
+size_t device_cap() {
+    const char* s = std::getenv("TFOCUS_MAX_DEVICE_BYTES");
+    if (!s || !*s) return (size_t)-1;
+    return (size_t)std::strtoull(s, nullptr, 10);
+}
+
+}  // namespace
+
+struct tf_solver {
+    tf_grid grid{};
+    int prec = TF_F32;
+    size_t esize = 4;
+    hipStream_t stream = nullptr;
+    long cells = 0;
+    int nkx = 0;
+    void* state = nullptr;
+    void* spec = nullptr;
+    void* tw[3] = {nullptr, nullptr, nullptr};
+    double* partials = nullptr;
+    size_t npartials = 0;
+    double* results = nullptr;     // 8 doubles
+    void* pulse_tab = nullptr;
+    void* scratch_out = nullptr;
+    size_t scratch_bytes = 0;
+    double t = 0.0;
+    bool project_b_next = false;
+    bool have_cutout = false;
+    double R_min = 0.0, R_max = 0.0;
+};
+
+namespace {
+
+tf::GridDev grid_dev(const tf_solver* s) {
+    tf::GridDev g;
+    g.nx = s->grid.nx; g.ny = s->grid.ny; g.nz = s->grid.nz;
+    g.dx = s->grid.dx; g.dy = s->grid.dy; g.dz = s->grid.dz;
+    g.x_min = s->grid.x_min; g.y_min = s->grid.y_min; g.z_min = s->grid.z_min;
+    return g;
+}
+
+tf::StepParams step_params(const tf_solver* s, double dt, bool project_b) {
+    tf::StepParams p;
+    const tf_grid& g = s->grid;
+    p.nx = g.nx; p.ny = g.ny; p.nz = g.nz; p.nkx = s->nkx;
+    p.kfx = 2.0 * M_PI / (g.nx * g.dx);
+    p.kfy = 2.0 * M_PI / (g.ny * g.dy);
+    p.kfz = 2.0 * M_PI / (g.nz * g.dz);
+    p.cdt = dt;
+    p.scale = 1.0 / ((double)g.nx * (double)g.ny * (double)g.nz);
+    p.project_b = project_b ? 1 : 0;
+    return p;
+}
+
+template <typename T>
+hipError_t forward_xy(tf_solver* s) {
+    const tf_grid& g = s->grid;
+    hipError_t e = tf::launch_x_forward<T>(static_cast<const T*>(s->state), s->spec, s->tw[0], g.nx, g.ny, g.nz, s->stream);
+    if (e != hipSuccess) return e;
+    return tf::launch_y_pass<T>(s->spec, s->tw[1], g.nx, g.ny, g.nz, -1, s->stream);
+}
+
+template <typename T>
+hipError_t one_step(tf_solver* s, double dt, bool project_b) {
+    const tf_grid& g = s->grid;
+    hipError_t e = forward_xy<T>(s);
+    if (e != hipSuccess) return e;
+    tf::StepParams p = step_params(s, dt, project_b);
+    e = tf::launch_z_pass<T>(s->spec, s->tw[2], p, tf::Z_STEP, nullptr, nullptr, s->stream);
+    if (e != hipSuccess) return e;
+    e = tf::launch_y_pass<T>(s->spec, s->tw[1], g.nx, g.ny, g.nz, +1, s->stream);
+    if (e != hipSuccess) return e;
+    return tf::launch_x_inverse<T>(s->spec, static_cast<T*>(s->state), s->tw[0], g.nx, g.ny, g.nz, s->stream);
+}
+
+hipError_t upload_twiddles(void* dst, int n, int prec, hipStream_t st) {
+    std::vector<double> t = twiddle_table(n);
+    if (prec == TF_F64) {
+        hipError_t e = hipMemcpyAsync(dst, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(st);
+    }
+    std::vector<float> f(t.size());
+    for (size_t i = 0; i < t.size(); ++i) f[i] = (float)t[i];
+    hipError_t e = hipMemcpyAsync(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
+
+void free_all(tf_solver* s) {
+    void* ptrs[] = {s->state, s->spec, s->tw[0], s->tw[1], s->tw[2], s->partials, s->results,
+                    s->pulse_tab, s->scratch_out};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tf_version(void) { return "tfocus 0.1"; }
+
+const char* tf_last_error(void) { return g_last_error.c_str(); }
+
+int32_t tf_supported_length(int32_t n) { return length_ok(n) ? 1 : 0; }
+
+tf_status tf_pulse_geometry(const tf_pulse* pulse, tf_pulse_info* info) {
+    if (!info) return fail(TF_EINVAL, "info is NULL");
+    tf_status st = validate_pulse(pulse);
+    if (st != TF_OK) return st;
+    geometry(pulse, info);
+    return TF_OK;
+}
+
+tf_status tf_layer_grid(const tf_pulse* pulse, int32_t nx, int32_t ny, int32_t nz, double dx, double dy,
+                        double dz, tf_grid* out) {
+    if (!out) return fail(TF_EINVAL, "out is NULL");
+    tf_status st = validate_pulse(pulse);
+    if (st != TF_OK) return st;
+    if (nx <= 0 || ny <= 0 || nz <= 0) return fail(TF_EINVAL, "grid sizes must be > 0");
+    if (!finite_pos(dx) || !finite_pos(dy) || !finite_pos(dz)) return fail(TF_EINVAL, "spacings must be > 0");
+    tf_pulse_info g;
+    geometry(pulse, &g);
+    const double D = nx * dx;
+    const double i0 = std::floor((g.R_min + D) / dx + 0.5);
+    std::memset(out, 0, sizeof(*out));
+    out->nx = nx; out->ny = ny; out->nz = nz;
+    out->dx = dx; out->dy = dy; out->dz = dz;
+    out->x_min = -i0 * dx;
+    out->y_min = -(double)(ny / 2) * dy;
+    out->z_min = -(double)(nz / 2) * dz;
+    return TF_OK;
+}
+
+tf_status tf_create(const tf_grid* grid, int32_t precision, void* hip_stream, tf_solver** out) {
+    if (!grid || !out) return fail(TF_EINVAL, "grid and out must not be NULL");
+    *out = nullptr;
+    if (precision != TF_F32 && precision != TF_F64) return fail(TF_EINVAL, "precision must be TF_F32 or TF_F64");
+    if (grid->nx % 2 != 0) return fail(TF_EINVAL, "nx must be even");
+    if (grid->nx <= 0 || grid->ny <= 0 || grid->nz <= 0) return fail(TF_EINVAL, "grid sizes must be > 0");
+    if (!finite_pos(grid->dx) || !finite_pos(grid->dy) || !finite_pos(grid->dz))
+        return fail(TF_EINVAL, "spacings must be finite and > 0");
+    if (!std::isfinite(grid->x_min) || !std::isfinite(grid->y_min) || !std::isfinite(grid->z_min))
+        return fail(TF_EINVAL, "grid origin must be finite");
+    for (int n : {grid->nx, grid->ny, grid->nz})
+        if (!length_ok(n))
+            return fail(TF_EUNSUPPORTED, "axis length " + std::to_string(n) +
+                                             " unsupported (products of 2 and 3, 8..1024)");
+    tf_solver* s = new tf_solver();
+    s->grid = *grid;
+    s->prec = precision;
+    s->esize = precision == TF_F64 ? 8 : 4;
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    s->cells = (long)grid->nx * grid->ny * grid->nz;
+    s->nkx = tf::nkx_of(grid->nx);
+    const size_t state_b = 6 * (size_t)s->cells * s->esize;
+    const size_t spec_b = (size_t)grid->nz * grid->ny * s->nkx * 6 * 2 * s->esize;
+    const int zb = precision == TF_F64 ? tf::z_pass_blocks<double>(grid->nx, grid->ny, grid->nz)
+                                       : tf::z_pass_blocks<float>(grid->nx, grid->ny, grid->nz);
+    s->npartials = std::max<size_t>(tf::SUMSQ_BLOCKS, (size_t)zb * 4);
+    const size_t tw_b = 2 * s->esize * (size_t)(grid->nx + grid->ny + grid->nz);
+    const size_t need = state_b + spec_b + tw_b + s->npartials * 8 + 64;
+    if (need > device_cap()) {
+        delete s;
+        return fail(TF_ENOMEM, "solver needs " + std::to_string(need) + " device bytes, above TFOCUS_MAX_DEVICE_BYTES");
+    }
+    auto alloc = [&](void** p, size_t b) -> tf_status {
+        hipError_t e = hipMalloc(p, b);
+        if (e == hipErrorOutOfMemory) return fail(TF_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+        if (e != hipSuccess) return fail(TF_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+        return TF_OK;
+    };
+    tf_status st = TF_OK;
+    if (st == TF_OK) st = alloc(&s->state, state_b);
+    if (st == TF_OK) st = alloc(&s->spec, spec_b);
+    const int ns[3] = {grid->nx, grid->ny, grid->nz};
+    for (int a = 0; a < 3 && st == TF_OK; ++a) st = alloc(&s->tw[a], 2 * s->esize * ns[a]);
+    if (st == TF_OK) st = alloc((void**)&s->partials, s->npartials * sizeof(double));
+    if (st == TF_OK) st = alloc((void**)&s->results, 8 * sizeof(double));
+    if (st != TF_OK) {
+        free_all(s);
+        delete s;
+        return st;
+    }
+    hipError_t e = hipMemsetAsync(s->state, 0, state_b, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->spec, 0, spec_b, s->stream);
+    for (int a = 0; a < 3 && e == hipSuccess; ++a) e = upload_twiddles(s->tw[a], ns[a], precision, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        free_all(s);
+        delete s;
+        return fail(TF_EDEVICE, std::string("initialising solver: ") + hipGetErrorString(e));
+    }
+    *out = s;
+    return TF_OK;
+}
+
+tf_status tf_destroy(tf_solver* s) {
+    if (!s) return TF_OK;
+    hipError_t e = hipStreamSynchronize(s->stream);
+    free_all(s);
+    delete s;
+    if (e != hipSuccess) return fail(TF_EDEVICE, std::string("tf_destroy: ") + hipGetErrorString(e));
+    return TF_OK;
+}
+
+tf_status tf_set_fields(tf_solver* s, const void* src, int32_t src_on_device, double t) {
+    if (!s || !src) return fail(TF_EINVAL, "solver and src must not be NULL");
+    if (!std::isfinite(t)) return fail(TF_EINVAL, "t must be finite");
+    const size_t b = 6 * (size_t)s->cells * s->esize;
+    TF_HIP(hipMemcpyAsync(s->state, src, b, src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          s->stream));
+    if (!src_on_device) TF_HIP(hipStreamSynchronize(s->stream));
+    s->t = t;
+    s->project_b_next = false;
+    return TF_OK;
+}
+
+tf_status tf_get_fields(tf_solver* s, void* dst, int32_t dst_on_device) {
+    if (!s || !dst) return fail(TF_EINVAL, "solver and dst must not be NULL");
+    const size_t b = 6 * (size_t)s->cells * s->esize;
+    TF_HIP(hipMemcpyAsync(dst, s->state, b, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                          s->stream));
+    if (!dst_on_device) TF_HIP(hipStreamSynchronize(s->stream));
+    return TF_OK;
+}
+
+tf_status tf_state_ptr(tf_solver* s, void** dev_ptr) {
+    if (!s || !dev_ptr) return fail(TF_EINVAL, "solver and dev_ptr must not be NULL");
+    *dev_ptr = s->state;
+    return TF_OK;
+}
+
+tf_status tf_set_pulse(tf_solver* s, const tf_pulse* pulse, tf_pulse_info* info) {
+    if (!s) return fail(TF_EINVAL, "solver is NULL");
+    tf_status st = validate_pulse(pulse);
+    if (st != TF_OK) return st;
+    tf_pulse_info g;
+    geometry(pulse, &g);
+    g.D = s->grid.nx * s->grid.dx;
+    g.overlap = g.D < g.D_min ? 1 : 0;
+    if (info) *info = g;
+    if (!(g.D > pulse->L)) return fail(TF_EDOMAIN, "layer period D = nx dx must exceed the pulse length L");
+
+    tf::PulseDev p{};
+    p.envelope = pulse->envelope;
+    p.transverse = pulse->transverse;
+    p.polarization = pulse->polarization;
+    p.lambda = pulse->wavelength;
+    p.R0 = pulse->R0;
+    p.L = pulse->L;
+    p.ncycles = pulse->ncycles;
+    p.theta = g.theta;
+    p.eps = pulse->eps;
+    p.A = g.A;
+    p.alpha_max = g.alpha_max;
+    p.cep = pulse->cep;
+    p.gnorm = 1.0;
+    if (pulse->polarization == TF_POL_RADIAL) {
+        p.nparts = 1;
+        p.amp[0] = 1.0;
+        p.d[0][0] = 1.0; p.d[0][1] = 0.0; p.d[0][2] = 0.0;
+        p.phase_off[0] = 0.0;
+    } else {
+        const double c = std::cos(pulse->pol_angle), sn = std::sin(pulse->pol_angle);
+        const double e = pulse->ellipticity;
+        const double nrm = std::sqrt(1.0 + e * e);
+        p.nparts = e != 0.0 ? 2 : 1;
+        p.amp[0] = 1.0 / nrm;
+        p.d[0][0] = 0.0; p.d[0][1] = c; p.d[0][2] = sn;
+        p.phase_off[0] = 0.0;
+        p.amp[1] = e / nrm;
+        p.d[1][0] = 0.0; p.d[1][1] = -sn; p.d[1][2] = c;
+        p.phase_off[1] = 0.5 * M_PI;
+    }
+    if (pulse->envelope == TF_ENV_SPECTRAL) {
+        std::vector<double> tab;
+        double gnorm = 0.0;
+        spectral_table(pulse, tab, gnorm);
+        if (!(gnorm > 0.0) || tab.empty()) return fail(TF_EINVAL, "spectral pulse has no samples above w = 0");
+        if (s->pulse_tab) {
+            TF_HIP(hipStreamSynchronize(s->stream));
+            TF_HIP(hipFree(s->pulse_tab));
+            s->pulse_tab = nullptr;
+        }
+        TF_HIP(hipMalloc(&s->pulse_tab, tab.size() * sizeof(double)));
+        TF_HIP(hipMemcpyAsync(s->pulse_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice,
+                              s->stream));
+        TF_HIP(hipStreamSynchronize(s->stream));
+        p.nfreq = (int)(tab.size() / 3);
+        p.spec = static_cast<const double*>(s->pulse_tab);
+        p.gnorm = gnorm;
+    }
+    tf::GridDev gd = grid_dev(s);
+    hipError_t e = s->prec == TF_F64 ? tf::launch_init_map<double>(static_cast<double*>(s->state), gd, p, s->stream)
+                                     : tf::launch_init_map<float>(static_cast<float*>(s->state), gd, p, s->stream);
+    if (e != hipSuccess) return fail(TF_EDEVICE, std::string("init kernel: ") + hipGetErrorString(e));
+    s->t = 0.0;
+    s->project_b_next = true;
+    s->have_cutout = true;
+    s->R_min = g.R_min;
+    s->R_max = g.R_max;
+    return TF_OK;
+}
+
+tf_status tf_set_cutout(tf_solver* s, double R_min, double R_max) {
+    if (!s) return fail(TF_EINVAL, "solver is NULL");
+    if (!finite_pos(R_min) || !(R_max > R_min) || !std::isfinite(R_max))
+        return fail(TF_EINVAL, "need 0 < R_min < R_max");
+    s->R_min = R_min;
+    s->R_max = R_max;
+    s->have_cutout = true;
+    return TF_OK;
+}
+
+tf_status tf_advance(tf_solver* s, int64_t nsteps, double dt) {
+    if (!s) return fail(TF_EINVAL, "solver is NULL");
+    if (nsteps < 0) return fail(TF_EINVAL, "nsteps must be >= 0");
+    if (!std::isfinite(dt)) return fail(TF_EINVAL, "dt must be finite");
+    for (int64_t i = 0; i < nsteps; ++i) {
+        const bool pb = s->project_b_next;
+        hipError_t e = s->prec == TF_F64 ? one_step<double>(s, dt, pb) : one_step<float>(s, dt, pb);
+        if (e != hipSuccess) return fail(TF_EDEVICE, std::string("step: ") + hipGetErrorString(e));
+        s->project_b_next = false;
+    }
+    s->t = s->t + (double)nsteps * dt;
+    return TF_OK;
+}
+
+tf_status tf_read_focal(tf_solver* s, const tf_window* w, void* dst, int32_t dst_on_device) {
+    if (!s || !w || !dst) return fail(TF_EINVAL, "solver, window and dst must not be NULL");
+    if (!s->have_cutout) return fail(TF_ESTATE, "no cut-out radii (call tf_set_pulse or tf_set_cutout)");
+    if (w->wx <= 0 || w->wy <= 0 || w->wz <= 0) return fail(TF_EINVAL, "window sizes must be > 0");
+    if (!std::isfinite(w->cx) || !std::isfinite(w->cy) || !std::isfinite(w->cz))
+        return fail(TF_EINVAL, "window centre must be finite");
+    const tf_grid& g = s->grid;
+    const long ic = (long)std::floor((w->cx - g.x_min) / g.dx + 0.5);
+    const long jc = (long)std::floor((w->cy - g.y_min) / g.dy + 0.5);
+    const long kc = (long)std::floor((w->cz - g.z_min) / g.dz + 0.5);
+    const long j0 = jc - w->wy / 2, j1 = j0 + w->wy - 1, k0 = kc - w->wz / 2, k1 = k0 + w->wz - 1;
+    if (j0 < 0 || j1 >= g.ny || k0 < 0 || k1 >= g.nz)
+        return fail(TF_EINVAL, "window leaves the transverse extent of the grid");
+    const size_t bytes = 6 * (size_t)w->wx * w->wy * w->wz * s->esize;
+    void* out = dst;
+    if (!dst_on_device) {
+        if (s->scratch_bytes < bytes) {
+            if (s->scratch_out) {
+                TF_HIP(hipStreamSynchronize(s->stream));
+                TF_HIP(hipFree(s->scratch_out));
+                s->scratch_out = nullptr;
+                s->scratch_bytes = 0;
+            }
+            TF_HIP(hipMalloc(&s->scratch_out, bytes));
+            s->scratch_bytes = bytes;
+        }
+        out = s->scratch_out;
+    }
+    tf::GridDev gd = grid_dev(s);
+    hipError_t e = s->prec == TF_F64
+                       ? tf::launch_readout<double>(static_cast<const double*>(s->state), static_cast<double*>(out), gd,
+                                                    w->wx, w->wy, w->wz, ic, jc, kc, s->t, s->R_min, s->R_max, s->stream)
+                       : tf::launch_readout<float>(static_cast<const float*>(s->state), static_cast<float*>(out), gd,
+                                                   w->wx, w->wy, w->wz, ic, jc, kc, s->t, s->R_min, s->R_max, s->stream);
+    if (e != hipSuccess) return fail(TF_EDEVICE, std::string("readout kernel: ") + hipGetErrorString(e));
+    if (!dst_on_device) {
+        TF_HIP(hipMemcpyAsync(dst, out, bytes, hipMemcpyDeviceToHost, s->stream));
+        TF_HIP(hipStreamSynchronize(s->stream));
+    }
+    return TF_OK;
+}
+
+tf_status tf_diagnostics(tf_solver* s, double* energy, double* max_div_e, double* max_div_b) {
+    if (!s) return fail(TF_EINVAL, "solver is NULL");
+    hipError_t e;
+    const size_t n = 6 * (size_t)s->cells;
+    e = s->prec == TF_F64 ? tf::launch_sumsq<double>(static_cast<const double*>(s->state), n, s->partials, tf::SUMSQ_BLOCKS, s->stream)
+                          : tf::launch_sumsq<float>(static_cast<const float*>(s->state), n, s->partials, tf::SUMSQ_BLOCKS, s->stream);
+    if (e == hipSuccess) e = tf::launch_reduce(s->partials, tf::SUMSQ_BLOCKS, 1, 0, 0, s->results, s->stream);
+    if (e == hipSuccess) e = s->prec == TF_F64 ? forward_xy<double>(s) : forward_xy<float>(s);
+    int nb = 0;
+    if (e == hipSuccess) {
+        tf::StepParams p = step_params(s, 0.0, false);
+        e = s->prec == TF_F64 ? tf::launch_z_pass<double>(s->spec, s->tw[2], p, tf::Z_DIAG, s->partials, &nb, s->stream)
+                              : tf::launch_z_pass<float>(s->spec, s->tw[2], p, tf::Z_DIAG, s->partials, &nb, s->stream);
+    }
+    for (int q = 0; q < 4 && e == hipSuccess; ++q) e = tf::launch_reduce(s->partials, nb, 4, q, 1, s->results + 1 + q, s->stream);
+    double h[5] = {0, 0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(h, s->results, sizeof(h), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return fail(TF_EDEVICE, std::string("diagnostics: ") + hipGetErrorString(e));
+    if (energy) *energy = h[0];
+    if (max_div_e) *max_div_e = h[3] > 0.0 ? h[1] / h[3] : 0.0;
+    if (max_div_b) *max_div_b = h[4] > 0.0 ? h[2] / h[4] : 0.0;
+    if (!std::isfinite(h[0])) return fail(TF_ENONFINITE, "field energy is not finite");
+    return TF_OK;
+}
+
+tf_status tf_time(const tf_solver* s, double* t) {
+    if (!s || !t) return fail(TF_EINVAL, "solver and t must not be NULL");
+    *t = s->t;
+    return TF_OK;
+}
+
+tf_status tf_get_grid(const tf_solver* s, tf_grid* grid) {
+    if (!s || !grid) return fail(TF_EINVAL, "solver and grid must not be NULL");
+    *grid = s->grid;
+    return TF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,321 @@
+"""ctypes binding of libtfocus (include/tfocus.h).
+
+Argument marshalling only: every computation runs in the HIP library.  The
+functions carry the C names; descriptors may be given as dicts (the keys of
+the C structs, enums as strings) and arrays as torch tensors (device memory,
+passed by data_ptr on the current stream) or numpy arrays (host memory).
+Failures raise ``TfError`` with the library's status and message.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libtfocus.so")
+
+TF_OK, TF_EINVAL, TF_EUNSUPPORTED, TF_ENOMEM, TF_EDEVICE, TF_ESTATE, TF_EDOMAIN, TF_ENONFINITE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "TF_OK", -1: "TF_EINVAL", -2: "TF_EUNSUPPORTED", -3: "TF_ENOMEM",
+                -4: "TF_EDEVICE", -5: "TF_ESTATE", -6: "TF_EDOMAIN", -7: "TF_ENONFINITE"}
+TF_F32, TF_F64 = 0, 1
+ENVELOPES = {"cos2": 0, "gauss": 1, "spectral": 2}
+TRANSVERSE = {"flattop": 0, "gauss": 1}
+POLARIZATION = {"linear": 0, "radial": 1}
+PRECISION = {"f32": TF_F32, "f64": TF_F64}
+
+
+class TfError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class tf_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("x_min", ctypes.c_double), ("y_min", ctypes.c_double), ("z_min", ctypes.c_double)]
+
+
+class tf_pulse(ctypes.Structure):
+    _fields_ = [("envelope", ctypes.c_int32), ("transverse", ctypes.c_int32),
+                ("polarization", ctypes.c_int32), ("nfreq", ctypes.c_int32)] + \
+               [(n, ctypes.c_double) for n in ("wavelength", "R0", "L", "ncycles", "f_number",
+                                                 "theta", "eps", "P0", "pol_angle", "ellipticity",
+                                                 "cep", "gdd", "tod", "bandwidth")]
+
+
+class tf_pulse_info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("theta", "A", "R_min", "R_max", "L", "D_min",
+                                                "alpha_max", "D")] + \
+               [("overlap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class tf_window(ctypes.Structure):
+    _fields_ = [("wx", ctypes.c_int32), ("wy", ctypes.c_int32), ("wz", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("cz", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "tf_version": ([], ctypes.c_char_p),
+    "tf_last_error": ([], ctypes.c_char_p),
+    "tf_supported_length": ([ctypes.c_int32], ctypes.c_int32),
+    "tf_pulse_geometry": ([ctypes.POINTER(tf_pulse), ctypes.POINTER(tf_pulse_info)], ctypes.c_int),
+    "tf_layer_grid": ([ctypes.POINTER(tf_pulse), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                       ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.POINTER(tf_grid)],
+                      ctypes.c_int),
+    "tf_create": ([ctypes.POINTER(tf_grid), ctypes.c_int32, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "tf_destroy": ([_P], ctypes.c_int),
+    "tf_set_fields": ([_P, _P, ctypes.c_int32, ctypes.c_double], ctypes.c_int),
+    "tf_get_fields": ([_P, _P, ctypes.c_int32], ctypes.c_int),
+    "tf_state_ptr": ([_P, ctypes.POINTER(_P)], ctypes.c_int),
+    "tf_set_pulse": ([_P, ctypes.POINTER(tf_pulse), ctypes.POINTER(tf_pulse_info)], ctypes.c_int),
+    "tf_set_cutout": ([_P, ctypes.c_double, ctypes.c_double], ctypes.c_int),
+    "tf_advance": ([_P, ctypes.c_int64, ctypes.c_double], ctypes.c_int),
+    "tf_read_focal": ([_P, ctypes.POINTER(tf_window), _P, ctypes.c_int32], ctypes.c_int),
+    "tf_diagnostics": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                        ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "tf_time": ([_P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "tf_get_grid": ([_P, ctypes.POINTER(tf_grid)], ctypes.c_int),
+}
+
+_lib = None
+
+
+def load():
+    """Load libtfocus.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is missing: build it with "
+                               "`python -m paper_2010_00409_amd.build`")
+        lib = ctypes.CDLL(LIBPATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+def _check(status):
+    if status != TF_OK:
+        raise TfError(status, load().tf_last_error().decode())
+
+
+# ---- descriptor conversion ----------------------------------------------------
+
+def grid_struct(g):
+    if isinstance(g, tf_grid):
+        return g
+    return tf_grid(int(g["nx"]), int(g["ny"]), int(g["nz"]), 0, float(g["dx"]), float(g["dy"]),
+                   float(g["dz"]), float(g["x_min"]), float(g["y_min"]), float(g["z_min"]))
+
+
+def grid_dict(s):
+    return {k: getattr(s, k) for k in ("nx", "ny", "nz", "dx", "dy", "dz", "x_min", "y_min", "z_min")}
+
+
+def pulse_struct(p):
+    if isinstance(p, tf_pulse):
+        return p
+    s = tf_pulse()
+    s.envelope = ENVELOPES[p["envelope"]]
+    s.transverse = TRANSVERSE[p["transverse"]]
+    s.polarization = POLARIZATION[p["polarization"]]
+    s.nfreq = int(p.get("nfreq", 256))
+    for k in ("wavelength", "R0", "L", "ncycles", "f_number", "theta", "eps", "P0", "pol_angle",
+              "ellipticity", "cep", "gdd", "tod", "bandwidth"):
+        setattr(s, k, float(p.get(k, 0.0)))
+    return s
+
+
+def info_dict(s):
+    d = {k: getattr(s, k) for k, _ in tf_pulse_info._fields_ if k != "reserved"}
+    d["overlap"] = bool(d["overlap"])
+    return d
+
+
+def window_struct(w):
+    if isinstance(w, tf_window):
+        return w
+    return tf_window(int(w["wx"]), int(w["wy"]), int(w["wz"]), 0,
+                     float(w["cx"]), float(w["cy"]), float(w["cz"]))
+
+
+def _buffer(a):
+    """(pointer, on_device, nbytes, itemsize) of a torch tensor or numpy array."""
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return a.data_ptr(), 1 if a.is_cuda else 0, a.numel() * a.element_size(), a.element_size()
+    import numpy as np
+    if not (isinstance(a, np.ndarray) and a.flags["C_CONTIGUOUS"]):
+        raise ValueError("need a C-contiguous numpy array or a contiguous tensor")
+    return a.ctypes.data, 0, a.nbytes, a.itemsize
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+# ---- C calls ------------------------------------------------------------------
+
+def tf_version():
+    return load().tf_version().decode()
+
+
+def tf_last_error():
+    return load().tf_last_error().decode()
+
+
+def tf_supported_length(n):
+    return bool(load().tf_supported_length(int(n)))
+
+
+def tf_pulse_geometry(pulse):
+    info = tf_pulse_info()
+    _check(load().tf_pulse_geometry(ctypes.byref(pulse_struct(pulse)), ctypes.byref(info)))
+    return info_dict(info)
+
+
+def tf_layer_grid(pulse, n, spacing):
+    out = tf_grid()
+    _check(load().tf_layer_grid(ctypes.byref(pulse_struct(pulse)), int(n[0]), int(n[1]), int(n[2]),
+                                float(spacing[0]), float(spacing[1]), float(spacing[2]),
+                                ctypes.byref(out)))
+    return grid_dict(out)
+
+
+def tf_create(grid, precision="f32", stream=None):
+    h = ctypes.c_void_p()
+    prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    _check(load().tf_create(ctypes.byref(grid_struct(grid)), prec, _stream_ptr(stream), ctypes.byref(h)))
+    return h
+
+
+def tf_destroy(h):
+    _check(load().tf_destroy(h))
+
+
+def tf_set_fields(h, src, t=0.0):
+    ptr, dev, _, _ = _buffer(src)
+    _check(load().tf_set_fields(h, ptr, dev, float(t)))
+
+
+def tf_get_fields(h, dst):
+    ptr, dev, _, _ = _buffer(dst)
+    _check(load().tf_get_fields(h, ptr, dev))
+    return dst
+
+
+def tf_state_ptr(h):
+    p = ctypes.c_void_p()
+    _check(load().tf_state_ptr(h, ctypes.byref(p)))
+    return p.value
+
+
+def tf_set_pulse(h, pulse):
+    info = tf_pulse_info()
+    _check(load().tf_set_pulse(h, ctypes.byref(pulse_struct(pulse)), ctypes.byref(info)))
+    return info_dict(info)
+
+
+def tf_set_cutout(h, R_min, R_max):
+    _check(load().tf_set_cutout(h, float(R_min), float(R_max)))
+
+
+def tf_advance(h, nsteps, dt):
+    _check(load().tf_advance(h, int(nsteps), float(dt)))
+
+
+def tf_read_focal(h, window, dst):
+    ptr, dev, _, _ = _buffer(dst)
+    _check(load().tf_read_focal(h, ctypes.byref(window_struct(window)), ptr, dev))
+    return dst
+
+
+def tf_diagnostics(h):
+    e, de, db = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(load().tf_diagnostics(h, ctypes.byref(e), ctypes.byref(de), ctypes.byref(db)))
+    return e.value, de.value, db.value
+
+
+def tf_time(h):
+    t = ctypes.c_double()
+    _check(load().tf_time(h, ctypes.byref(t)))
+    return t.value
+
+
+def tf_get_grid(h):
+    g = tf_grid()
+    _check(load().tf_get_grid(h, ctypes.byref(g)))
+    return grid_dict(g)
+
+
+class Solver:
+    """Owning wrapper of a tf_solver handle."""
+
+    def __init__(self, grid, precision="f32", stream=None):
+        self.precision = precision
+        self.grid = grid_dict(grid_struct(grid))
+        self.h = tf_create(grid, precision, stream)
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            tf_destroy(self.h)
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        g = self.grid
+        return (6, g["nz"], g["ny"], g["nx"])
+
+    def set_fields(self, src, t=0.0):
+        tf_set_fields(self.h, src, t)
+
+    def get_fields(self, dst):
+        return tf_get_fields(self.h, dst)
+
+    def set_pulse(self, pulse):
+        return tf_set_pulse(self.h, pulse)
+
+    def set_cutout(self, R_min, R_max):
+        tf_set_cutout(self.h, R_min, R_max)
+
+    def advance(self, nsteps, dt):
+        tf_advance(self.h, nsteps, dt)
+
+    def read_focal(self, window, dst):
+        return tf_read_focal(self.h, window, dst)
+
+    def diagnostics(self):
+        return tf_diagnostics(self.h)
+
+    @property
+    def t(self):
+        return tf_time(self.h)
+
+    def state_ptr(self):
+        return tf_state_ptr(self.h)

@@ -1,0 +1,102 @@
+"""The C ABI without a GPU: the library loads, exports every entry point the
+header declares, validates arguments before touching HIP, and its host-side
+geometry (Sec. II.B-II.C) agrees with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import pulse as opulse
+from paper_2010_00409_amd import tfocus as tf
+from synthetic import configs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "tfocus.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tf_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_entry_point():
+    lib = tf.load()
+    names = header_functions()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(tf.exported_names())
+
+
+def test_version_and_supported_lengths():
+    assert tf.tf_version().startswith("tfocus")
+    for n in (8, 16, 24, 64, 96, 192, 512, 768, 1024):
+        assert tf.tf_supported_length(n)
+    for n in (4, 10, 100, 2048, 80, 1536):
+        assert not tf.tf_supported_length(n)
+
+
+@pytest.mark.parametrize("grid, prec, status", [
+    (dict(configs.cube_grid(64, 0.1), nx=63), "f32", tf.TF_EINVAL),
+    (dict(configs.cube_grid(64, 0.1), nx=100), "f32", tf.TF_EUNSUPPORTED),
+    (dict(configs.cube_grid(64, 0.1), ny=2048), "f32", tf.TF_EUNSUPPORTED),
+    (dict(configs.cube_grid(64, 0.1), dx=0.0), "f32", tf.TF_EINVAL),
+    (dict(configs.cube_grid(64, 0.1), dz=float("nan")), "f64", tf.TF_EINVAL),
+    (configs.cube_grid(64, 0.1), 7, tf.TF_EINVAL),
+])
+def test_create_rejects_bad_descriptors(grid, prec, status):
+    with pytest.raises(tf.TfError) as ei:
+        tf.tf_create(grid, prec)
+    assert ei.value.status == status
+    assert tf.tf_last_error()
+
+
+def test_device_byte_cap_gives_enomem_before_any_hip_call(monkeypatch):
+    monkeypatch.setenv("TFOCUS_MAX_DEVICE_BYTES", "1000000")
+    with pytest.raises(tf.TfError) as ei:
+        tf.tf_create(configs.cube_grid(64, 0.1), "f32")
+    assert ei.value.status == tf.TF_ENOMEM
+
+
+@pytest.mark.parametrize("bad, status", [
+    (dict(wavelength=0.0), tf.TF_EINVAL),
+    (dict(R0=0.5, L=2.0), tf.TF_EINVAL),
+    (dict(theta=0.0, f_number=0.0), tf.TF_EINVAL),
+    (dict(envelope="spectral", nfreq=0), tf.TF_EINVAL),
+    (dict(polarization="radial", ellipticity=0.5), tf.TF_EINVAL),
+])
+def test_pulse_validation(bad, status):
+    with pytest.raises(tf.TfError) as ei:
+        tf.tf_pulse_geometry(configs.pulse(**bad))
+    assert ei.value.status == status
+
+
+def test_null_pointers_are_rejected():
+    lib = tf.load()
+    assert lib.tf_create(None, 0, None, None) == tf.TF_EINVAL
+    assert lib.tf_advance(None, 1, 0.1) == tf.TF_EINVAL
+    assert lib.tf_read_focal(None, None, None, 0) == tf.TF_EINVAL
+    assert lib.tf_destroy(None) == tf.TF_OK
+
+
+@pytest.mark.parametrize("kw", [
+    dict(f_number=0.3), dict(f_number=0.5, eps=0.2), dict(theta=0.9, R0=6.0, L=10.0),
+    dict(transverse="gauss", f_number=1.0), dict(transverse="gauss", f_number=0.25, R0=20.0, L=24.0),
+])
+def test_pulse_geometry_matches_oracle(kw):
+    p = configs.pulse(**kw)
+    got = tf.tf_pulse_geometry(p)
+    ref = opulse.geometry(p)
+    for k in ("theta", "R_min", "R_max", "L", "D_min", "alpha_max"):
+        assert got[k] == pytest.approx(ref[k], rel=1e-15, abs=1e-15), k
+    assert got["A"] == pytest.approx(ref["A"], rel=1e-12)
+
+
+@pytest.mark.parametrize("n, d", [((56, 64, 64), 0.125), ((256, 256, 256), 0.125),
+                                  ((512, 512, 512), 1 / 12), ((42, 30, 18), 0.3)])
+def test_layer_grid_matches_oracle(n, d):
+    for p in (configs.c2()["pulse"], configs.c3()["pulse"], configs.pulse()):
+        got = tf.tf_layer_grid(p, n, (d, d, d))
+        ref = opulse.layer_grid(p, n, (d, d, d))
+        assert got == ref

@@ -1,0 +1,193 @@
+"""GPU parity: the HIP path through the C ABI against the float64 oracle on
+the same seeded inputs.  Tolerances (relative L2 over all six components):
+float64 <= 1e-12, float32 <= 1e-5 per step."""
+import numpy as np
+import pytest
+
+from oracle import mapping, psatd, pulse
+from paper_2010_00409_amd import tfocus as tf
+from synthetic import configs, planewaves
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32_TOL = 1e-5
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def spacing(g):
+    return (g["dz"], g["dy"], g["dx"])
+
+
+def run_gpu(grid, prec, state, nsteps, dt, t0=0.0):
+    dtype = np.float64 if prec == "f64" else np.float32
+    with tf.Solver(grid, prec) as s:
+        s.set_fields(np.ascontiguousarray(state, dtype=dtype), t0)
+        s.advance(nsteps, dt)
+        out = np.empty(s.shape, dtype=dtype)
+        s.get_fields(out)
+        return out, s.t
+
+
+def transverse_state(seed, shape, d):
+    g = dict(nx=shape[2], ny=shape[1], nz=shape[0], dx=d, dy=d, dz=d, x_min=0.0, y_min=0.0, z_min=0.0)
+    E, B = planewaves.random_fields(seed, shape)
+    E, B = psatd.step_fft(E, B, spacing(g), 0.0, project_b_first=True)
+    return g, np.concatenate([E, B])
+
+
+def test_roundtrip_is_bitwise():
+    g = configs.cube_grid(32, 0.25)
+    for prec, dt in (("f64", np.float64), ("f32", np.float32)):
+        x = np.random.default_rng(0).standard_normal((6, 32, 32, 32)).astype(dt)
+        out, t = run_gpu(g, prec, x, 0, 0.1, t0=1.5)
+        assert np.array_equal(out, x) and t == 1.5
+
+
+def test_C1_planewaves_f64_64_steps_match_oracle_and_closed_form():
+    c = configs.c1()
+    g = c["grid"]
+    modes = planewaves.draw(c["planewave_seed"], nmodes=16, mmax=31)
+    E, B = planewaves.fields(modes, g)
+    out, t = run_gpu(g, "f64", np.concatenate([E, B]), c["steps"], c["dt"])
+    Eo, Bo = psatd.step_fft(E, B, spacing(g), c["dt"], nsteps=c["steps"])
+    ref = np.concatenate([Eo, Bo])
+    assert rel(out, ref) <= F64_TOL
+    assert t == 0.0 + c["steps"] * c["dt"]
+
+
+def test_C1_pulse_f64_init_and_64_steps_match_oracle():
+    c = configs.c1()
+    g = c["grid"]
+    with tf.Solver(g, "f64") as s:
+        info = s.set_pulse(c["pulse"])
+        init = np.empty(s.shape)
+        s.get_fields(init)
+        s.advance(c["steps"], c["dt"])
+        out = np.empty(s.shape)
+        s.get_fields(out)
+    E, B = pulse.init_fields(c["pulse"], g)
+    ref0 = np.concatenate([E, B])
+    assert rel(init, ref0) <= F64_TOL
+    assert np.abs(init).max() > 0.01
+    Eo, Bo = psatd.step_fft(E, B, spacing(g), c["dt"], nsteps=c["steps"], project_b_first=True)
+    assert rel(out, np.concatenate([Eo, Bo])) <= F64_TOL
+    assert info["R_min"] == pulse.geometry(c["pulse"])["R_min"]
+
+
+SHAPES = [(8, 8, 8), (16, 24, 32), (8, 8, 1024), (8, 1024, 8), (1024, 8, 8), (24, 48, 96),
+          (12 * 2, 16, 768), (16, 384, 8), (192, 8, 16), (64, 64, 64), (32, 128, 256), (16, 512, 16),
+          (512, 16, 8)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"{s[2]}x{s[1]}x{s[0]}" for s in SHAPES])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_one_step_every_axis_length(shape, prec):
+    """shape = (nz, ny, nx); one step of a random transverse field (plus a
+    second with the B projection) against the oracle."""
+    g, st = transverse_state(sum(shape), shape, 0.37)
+    dtype = np.float64 if prec == "f64" else np.float32
+    st = st.astype(dtype).astype(np.float64)
+    out, _ = run_gpu(g, prec, st, 1, 0.61)
+    Eo, Bo = psatd.step_fft(st[:3], st[3:], spacing(g), 0.61)
+    assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= (F64_TOL if prec == "f64" else F32_TOL)
+
+
+def test_f32_step_random_longitudinal_input_and_b_projection():
+    """Unstructured input: the step must also remove longitudinal E (Eq. (3))
+    and, on the first step after a pulse, longitudinal B."""
+    shape = (32, 48, 64)
+    g = dict(nx=64, ny=48, nz=32, dx=0.3, dy=0.25, dz=0.2, x_min=-1.0, y_min=2.0, z_min=0.5)
+    x = np.random.default_rng(5).standard_normal((6,) + shape).astype(np.float32)
+    out, _ = run_gpu(g, "f32", x, 1, 0.45)
+    Eo, Bo = psatd.step_fft(x[:3].astype(np.float64), x[3:].astype(np.float64), spacing(g), 0.45)
+    assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= F32_TOL
+
+
+@pytest.mark.parametrize("envelope, transverse, pol", [
+    ("cos2", "flattop", "linear"), ("gauss", "gauss", "linear"), ("spectral", "flattop", "radial"),
+    ("spectral", "gauss", "linear")])
+def test_init_map_f64_matches_oracle(envelope, transverse, pol):
+    p = configs.pulse(envelope=envelope, transverse=transverse, polarization=pol, R0=5.0, L=3.0,
+                      f_number=0.6, ncycles=1.5, bandwidth=0.4, gdd=0.3, tod=0.05, cep=0.8,
+                      ellipticity=0.0 if pol == "radial" else 0.4, pol_angle=0.3, nfreq=96)
+    g = pulse.layer_grid(p, (24, 64, 48), (0.2, 0.21, 0.22))     # D = 4.8 < D_min: overlap
+    with tf.Solver(g, "f64") as s:
+        info = s.set_pulse(p)
+        out = np.empty(s.shape)
+        s.get_fields(out)
+    E, B = pulse.init_fields(p, g)
+    ref = np.concatenate([E, B])
+    assert np.abs(ref).max() > 0.01
+    assert rel(out, ref) <= F64_TOL
+    assert info["overlap"] == (info["D"] < info["D_min"])
+
+
+def test_readout_matches_oracle_bitwise_f64():
+    p = configs.pulse(envelope="cos2", R0=4.0, L=2.0, theta=1.0)
+    g = pulse.layer_grid(p, (48, 64, 64), (0.125, 0.125, 0.125))
+    geo = pulse.geometry(p)
+    win = dict(wx=40, wy=36, wz=30, cx=0.3, cy=-0.2, cz=0.1)
+    for T in (0.0, 1.7, 4.0, 6.5):
+        with tf.Solver(g, "f64") as s:
+            s.set_pulse(p)
+            s.advance(1, T)
+            full = np.empty(s.shape)
+            s.get_fields(full)
+            out = np.empty((6, 30, 36, 40))
+            s.read_focal(win, out)
+            tt = s.t
+        ref = mapping.readout(full, g, win, tt, geo["R_min"], geo["R_max"])
+        assert np.array_equal(out, ref)
+
+
+def test_readout_rejects_window_outside_grid():
+    g = configs.cube_grid(32, 0.25)
+    with tf.Solver(g, "f32") as s:
+        s.set_cutout(1.0, 2.0)
+        with pytest.raises(tf.TfError) as ei:
+            s.read_focal(dict(wx=8, wy=40, wz=8, cx=0, cy=0, cz=0), np.empty((6, 8, 40, 8), np.float32))
+        assert ei.value.status == tf.TF_EINVAL
+    with tf.Solver(g, "f32") as s:
+        with pytest.raises(tf.TfError) as ei:
+            s.read_focal(dict(wx=8, wy=8, wz=8, cx=0, cy=0, cz=0), np.empty((6, 8, 8, 8), np.float32))
+        assert ei.value.status == tf.TF_ESTATE
+
+
+def test_diagnostics_energy_and_divergence():
+    g, st = transverse_state(21, (32, 32, 32), 0.3)
+    with tf.Solver(g, "f64") as s:
+        s.set_fields(st)
+        e0, de, db = s.diagnostics()
+        assert e0 == pytest.approx(psatd.energy(st[:3], st[3:]), rel=1e-13)
+        assert de < 1e-13 and db < 1e-13
+        s.advance(20, 0.77)
+        e1, de1, db1 = s.diagnostics()
+        assert e1 == pytest.approx(e0, rel=1e-12)
+        assert de1 < 1e-12 and db1 < 1e-12
+    x = np.random.default_rng(3).standard_normal((6, 32, 32, 32))
+    with tf.Solver(g, "f64") as s:
+        s.set_fields(x)
+        _, de, db = s.diagnostics()
+        rde, rdb = psatd.max_divergence(x[:3], x[3:], spacing(g))
+        assert de == pytest.approx(rde, rel=1e-10) and db == pytest.approx(rdb, rel=1e-10)
+
+
+def test_reversibility_and_semigroup_on_gpu_f32():
+    g, st = transverse_state(22, (64, 64, 64), 0.25)
+    st = st.astype(np.float32)
+    fwd, _ = run_gpu(g, "f32", st, 10, 0.3)
+    back, _ = run_gpu(g, "f32", fwd, 10, -0.3)
+    assert rel(back.astype(np.float64), st.astype(np.float64)) < 1e-5
+    jump, _ = run_gpu(g, "f32", st, 1, 3.0)
+    assert rel(fwd.astype(np.float64), jump.astype(np.float64)) < 1e-5
+
+
+def test_determinism_bitwise():
+    g, st = transverse_state(23, (64, 64, 64), 0.25)
+    a, _ = run_gpu(g, "f32", st.astype(np.float32), 3, 0.4)
+    b, _ = run_gpu(g, "f32", st.astype(np.float32), 3, 0.4)
+    assert np.array_equal(a, b)

@@ -1,0 +1,172 @@
+"""Benchmark of the headline workload on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload (C3): a 512^3 float32 periodic layer, dx = lambda/12, a two-octave
+single-cycle spectral pulse (f = 0.5, radial polarisation) put on the
+focusing sphere and mapped into the layer, 1000 spectral steps of
+dt = lambda/24, then the 64^3 focal window read through the cut-out.  One
+bench "step" is one such run (init + 1000 steps + readout); W runs are
+untimed, K runs are timed between device synchronisations.  Inputs are
+synthetic and generated on the device by the library.
+
+Printed: one JSON line with the whole-run throughput in cell-updates/s, the
+roofline of the dominant kernel (algorithmic bytes over its mean launch time
+from HIP events recorded around every launch in the timed region), and the
+CPU oracle timed on this host on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "PSATD cell-updates/s + HBM GB/s at 512^3 FP32; surrogate speedup at 1e-2 err"
+PASS_BYTES_PER_CELL = {"f32": 48, "f64": 96}   # read + write of six components
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2, help="timed runs")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed runs")
+    ap.add_argument("--psatd-steps", type=int, default=None, help="override steps per run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2"])
+    return ap.parse_args()
+
+
+def traffic_record(kernel):
+    """HBM bytes per launch measured by rocprofv3 counters for this kernel,
+    if recorded against the current kernel source (else None)."""
+    path = os.path.join(HERE, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    import hashlib
+    rec = json.load(open(path)).get(kernel)
+    if not rec:
+        return None
+    src = os.path.join(HERE, "paper_2010_00409_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(src)):
+        if f.endswith((".hip", ".h", ".inc")):
+            h.update(open(os.path.join(src, f), "rb").read())
+    if rec.get("source_sha256") != h.hexdigest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(n, seed=3):
+    """The oracle's spectral step (float64 real FFTs, Eqs. (3)-(4)) on one
+    n^3 state with random fields: a bounded sample of the workload's step."""
+    import numpy as np
+    from oracle import psatd
+    rng = np.random.default_rng(seed)
+    E = rng.standard_normal((3, n, n, n))
+    B = rng.standard_normal((3, n, n, n))
+    d = 1.0 / 12.0
+    cores = psatd._workers()
+    t0 = time.perf_counter()
+    psatd.step_fft(E, B, (d, d, d), 1.0 / 24.0, workers=cores)
+    dt = time.perf_counter() - t0
+    return {"value": n ** 3 / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"one float64 oracle step (scipy rfftn -> Eqs. (3)-(4) -> irfftn, "
+                      f"{cores} workers) of a {n}^3 six-component state: {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2010_00409_amd import tfocus as tf
+    from synthetic import configs
+
+    cfg = configs.c3() if args.workload == "c3" else configs.c2()
+    n = cfg["n"]
+    steps = args.psatd_steps or cfg["steps"]
+    prec = cfg["precision"]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    grid = tf.tf_layer_grid(cfg["pulse"], n, cfg["spacing"])
+    win = cfg["window"]
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    out = torch.empty((6, win["wz"], win["wy"], win["wx"]), dtype=dtype, device="cuda")
+    cells = n[0] * n[1] * n[2]
+
+    with tf.Solver(grid, prec, stream) as s:
+        def run():
+            s.set_pulse(cfg["pulse"])
+            s.advance(steps, cfg["dt"])
+            s.read_focal(win, out)
+
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        s.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            run()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = s.profile_read()
+        s.profile(False)
+        peak_field = float(out.abs().max().item())
+
+    elapsed = t1 - t0
+    cell_updates = cells * steps * args.steps
+    value = cell_updates / elapsed
+    passes = {k: v for k, v in prof.items() if v[1] > 0}
+    step_passes = ("x_forward", "y_forward", "z_step", "y_inverse", "x_inverse")
+    dom = max(step_passes, key=lambda k: passes.get(k, (0.0, 0))[0])
+    dom_ms, dom_n = passes[dom]
+    per_launch_s = dom_ms / dom_n / 1e3
+    alg_bytes = PASS_BYTES_PER_CELL[prec] * cells
+    achieved = alg_bytes / per_launch_s / 1e9
+    traffic = traffic_record(dom)
+    step_ms = sum(passes[k][0] for k in step_passes) / (steps * args.steps)
+    hbm_gbs = PASS_BYTES_PER_CELL[prec] * len(step_passes) * cells / (step_ms / 1e3) / 1e9
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{cfg['name']}: {n[0]}^3 {prec} periodic layer, dx = lambda/{round(1 / cfg['spacing'][0])}, "
+                         f"spectral pulse mapped into the layer, {steps} steps of dt = {cfg['dt']:.6g}, "
+                         f"64^3 focal window; one bench step = init + {steps} steps + readout"),
+            "grid": list(n), "psatd_steps_per_run": steps, "precision": prec,
+            "twiddles_and_phases": "float64-built",
+        },
+        "hbm_gbs_pass_model": hbm_gbs,
+        "ms_per_psatd_step": step_ms,
+        "passes_ms_per_launch": {k: v[0] / v[1] for k, v in passes.items()},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": traffic, "alg_bytes_per_launch": alg_bytes},
+        "focal_peak_abs": peak_field,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(n[0])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -210,6 +210,23 @@ tf_status tf_time(const tf_solver* s, double* t);
 /* Grid the solver was created with. */
 tf_status tf_get_grid(const tf_solver* s, tf_grid* grid);
 
+
+/* Pass kinds reported by tf_profile_read. */
+typedef enum {
+    TF_PASS_X_FORWARD = 0, TF_PASS_Y_FORWARD = 1, TF_PASS_Z_STEP = 2, TF_PASS_Y_INVERSE = 3,
+    TF_PASS_X_INVERSE = 4, TF_PASS_INIT = 5, TF_PASS_READOUT = 6, TF_PASS_OTHER = 7,
+    TF_NPASS = 8
+} tf_pass;
+
+/* Start (enable = 1) or stop (0) timing every kernel launch of the solver
+ * with a pair of HIP events on its stream.  Enabling clears earlier records. */
+tf_status tf_profile(tf_solver* s, int32_t enable);
+
+/* Synchronise and report, per tf_pass kind, the summed kernel time in ms and
+ * the number of launches recorded since profiling was enabled.  Either
+ * array (TF_NPASS entries) may be NULL. */
+tf_status tf_profile_read(tf_solver* s, double* ms_total, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -159,6 +159,89 @@ __device__ __forceinline__ void fft_lds(C2<T>* buf, const C2<T>* tw, int tid) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Lane-group FFT.  A transform of length N is held by G = N / E consecutive
+// threads ("lanes" u = 0..G-1), E elements each, in the cyclic layout
+// x[e] = data[u + G e].  Every Stockham stage reads this layout (constant
+// geometry), so stage inputs come straight from registers; outputs are
+// exchanged through an LDS region of the group, except after the last stage,
+// whose outputs land back in the cyclic layout in registers.  Radices must
+// divide E (each lane then runs E / R butterflies per stage).
+template <int N, int E> struct LGPlan {
+    static constexpr int a = log2_part(N);
+    static constexpr int b = log3_part(N);
+    static constexpr int ea = log2_part(E);
+    static constexpr int eb = log3_part(E);
+    // radix-8 stages if 8 | E, then one 4 or 2, then radix-3 stages
+    static constexpr int r8 = (ea >= 3) ? a / 3 : 0;
+    static constexpr int rest = a - 3 * r8;              // remaining power of two
+    static constexpr int n4 = (ea >= 2) ? rest / 2 : 0;
+    static constexpr int n2 = rest - 2 * n4;
+    static constexpr int nst = r8 + n4 + n2 + b;
+    static constexpr int radix(int s) {
+        return s < r8 ? 8 : (s < r8 + n4 ? 4 : (s < r8 + n4 + n2 ? 2 : 3));
+    }
+    static_assert(b == 0 || eb >= 1, "radix-3 stages need 3 | E");
+    static_assert(N % E == 0 && (N / E) <= 1024, "bad lane-group shape");
+};
+
+// Element n of a lane-group's LDS region sits at base[n * S + (n >> 5) * S2]:
+// S2 = 1 adds one pad slot every 32 elements (contiguous regions), S > 1
+// interleaves the regions of neighbouring groups (column tiles).
+template <int N, int S, int S2> struct LgAt {
+    __device__ __forceinline__ static int at(int n) { return n * S + (n >> 5) * S2; }
+    static constexpr int span = (N - 1) * S + ((N - 1) >> 5) * S2 + 1;
+};
+
+template <typename T, int N, int E, int R, int NS, int DIR, int S, int S2, int TWN>
+__device__ __forceinline__ void lg_stage_tw(C2<T> (&x)[E], C2<T>* reg, const C2<T>* tw, int u) {
+    constexpr int G = N / E, Q = E / R;
+    constexpr bool LAST = (NS * R == N);
+    using A = LgAt<N, S, S2>;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int j = u + G * q;
+        C2<T> v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = x[q + Q * r];
+        const int jm = j % NS;
+        if constexpr (NS > 1) {
+            constexpr int STEP = (TWN / N) * (N / (NS * R));
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                C2<T> w = tw[r * jm * STEP];
+                if (DIR > 0) w = cconj(w);
+                v[r] = cmul(v[r], w);
+            }
+        }
+        dftR<T, R, DIR>(v);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[q + Q * r] = v[r];
+        } else {
+            const int base = (j / NS) * NS * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r) reg[A::at(base + r * NS)] = v[r];
+        }
+    }
+    if constexpr (!LAST) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = reg[A::at(u + G * e)];
+        __syncthreads();
+    }
+}
+
+// tw: table of TWN entries exp(-2 pi i e / TWN), TWN a multiple of N.
+template <typename T, int N, int E, int DIR, int S, int S2, int TWN = N, int ST = 0, int NS = 1>
+__device__ __forceinline__ void lg_fft(C2<T> (&x)[E], C2<T>* reg, const C2<T>* tw, int u) {
+    if constexpr (ST < LGPlan<N, E>::nst) {
+        constexpr int R = LGPlan<N, E>::radix(ST);
+        lg_stage_tw<T, N, E, R, NS, DIR, S, S2, TWN>(x, reg, tw, u);
+        lg_fft<T, N, E, DIR, S, S2, TWN, ST + 1, NS * R>(x, reg, tw, u);
+    }
+}
+
 // Copy a twiddle table of N entries into LDS (caller synchronises).
 template <typename T, int N, int NT>
 __device__ __forceinline__ void load_twiddles(C2<T>* dst, const C2<T>* __restrict__ src, int tid) {

@@ -5,10 +5,19 @@
 
 namespace tf {
 
-// Spectral layout: S[kz][ky][kx][c], kx in [0, nkx) with nkx = nx/2 + 1
-// rounded up to a multiple of 4 (slots beyond nx/2 are held at zero), c the
-// six field components; one mode's six components are contiguous.
-inline int nkx_of(int nx) { return ((nx / 2 + 1) + 3) / 4 * 4; }
+// Spectral layout: rows of nkx = nx/2 mode slots x 6 components (complex);
+// slot 0 packs the x DC and Nyquist planes as F(0) + i F(nx/2).  Row (kz, ky)
+// sits at RowMap::row: y is split into blocks of G rows, so rows are ordered
+// [ky / G][kz][ky % G]; z neighbours are G rows apart and y neighbours within
+// a block are adjacent.
+inline int nkx_of(int nx) { return nx / 2; }
+
+struct RowMap {
+    int ny, nz, G;
+    __host__ __device__ __forceinline__ long row(int z, int y) const {
+        return ((long)(y / G) * nz + z) * G + (y % G);
+    }
+};
 
 struct StepParams {
     int nx, ny, nz, nkx;
@@ -22,20 +31,23 @@ enum ZMode { Z_STEP = 0, Z_DIAG = 1 };
 
 // Forward x pass: real state [6][nz][ny][nx] -> spectral (x transformed).
 template <typename T> hipError_t launch_x_forward(const T* real, void* spec, const void* tw,
-                                                  int nx, int ny, int nz, hipStream_t st);
+                                                  int nx, int ny, int nz, RowMap rm, hipStream_t st);
 // Inverse x pass: spectral -> real state.
 template <typename T> hipError_t launch_x_inverse(const void* spec, T* real, const void* tw,
-                                                  int nx, int ny, int nz, hipStream_t st);
+                                                  int nx, int ny, int nz, RowMap rm, hipStream_t st);
 // In-place y transform of the spectral array, dir = -1 forward, +1 inverse.
+// fast = false forces the generic kernels.
 template <typename T> hipError_t launch_y_pass(void* spec, const void* tw, int nx, int ny, int nz,
-                                               int dir, hipStream_t st);
+                                               int dir, RowMap rm, bool fast, hipStream_t st);
 // z pass: Z_STEP = forward z FFT, Eqs. (3)-(4) update, inverse z FFT, in place;
 // Z_DIAG = forward z FFT and per-block maxima |k.E|, |k.B|, |E|, |B| into
-// partials (4 doubles per block), no store.  Returns the block count in *nblocks.
+// partials (4 doubles per block; the packed kx = 0 slot goes through dc, a
+// buffer of ny nz 6 complex elements), no store.  *nblocks receives the
+// number of 4-wide partials written.
 template <typename T> hipError_t launch_z_pass(void* spec, const void* tw, const StepParams& p,
-                                               int mode, double* partials, int* nblocks,
-                                               hipStream_t st);
-template <typename T> int z_pass_blocks(int nx, int ny, int nz);
+                                               RowMap rm, int mode, double* partials, void* dc,
+                                               int* nblocks, bool fast, hipStream_t st);
+template <typename T> int z_diag_blocks(int nx, int ny, int nz);
 
 // Twiddle tables are per axis length: tw[e] = exp(-2 pi i e / n).
 bool fft_length_supported(int n);

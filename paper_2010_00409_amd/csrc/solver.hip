@@ -2,6 +2,7 @@
 // pulse geometry, twiddle tables, buffers and the step driver.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -163,12 +164,19 @@ struct tf_solver {
     size_t npartials = 0;
     double* results = nullptr;     // 8 doubles
     void* pulse_tab = nullptr;
+    void* dcbuf = nullptr;         // diagnostics: packed kx = 0 slot after the forward z FFT
+    tf::RowMap rm{};
+    bool fast = true;              // use the specialised float32 column kernels
     void* scratch_out = nullptr;
     size_t scratch_bytes = 0;
     double t = 0.0;
     bool project_b_next = false;
     bool have_cutout = false;
     double R_min = 0.0, R_max = 0.0;
+    // per-launch timing (tf_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> evpool;
+    std::vector<int> rec_kind;
 };
 
 namespace {
@@ -194,25 +202,58 @@ tf::StepParams step_params(const tf_solver* s, double dt, bool project_b) {
     return p;
 }
 
-template <typename T>
-hipError_t forward_xy(tf_solver* s) {
-    const tf_grid& g = s->grid;
-    hipError_t e = tf::launch_x_forward<T>(static_cast<const T*>(s->state), s->spec, s->tw[0], g.nx, g.ny, g.nz, s->stream);
+// Runs launch() and, while profiling, brackets it with a pair of events.
+template <class F>
+hipError_t timed(tf_solver* s, int kind, F launch) {
+    if (!s->prof) return launch();
+    const size_t i = s->rec_kind.size();
+    while (s->evpool.size() < 2 * (i + 1)) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) return e;
+        s->evpool.push_back(ev);
+    }
+    hipError_t e = hipEventRecord(s->evpool[2 * i], s->stream);
     if (e != hipSuccess) return e;
-    return tf::launch_y_pass<T>(s->spec, s->tw[1], g.nx, g.ny, g.nz, -1, s->stream);
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(s->evpool[2 * i + 1], s->stream);
+    if (e == hipSuccess) s->rec_kind.push_back(kind);
+    return e;
+}
+
+template <typename T>
+hipError_t forward_xy(tf_solver* s, int kind_x, int kind_y) {
+    const tf_grid& g = s->grid;
+    hipError_t e = timed(s, kind_x, [&] {
+        return tf::launch_x_forward<T>(static_cast<const T*>(s->state), s->spec, s->tw[0], g.nx, g.ny, g.nz, s->rm,
+                                       s->stream);
+    });
+    if (e != hipSuccess) return e;
+    return timed(s, kind_y, [&] {
+        return tf::launch_y_pass<T>(s->spec, s->tw[1], g.nx, g.ny, g.nz, -1, s->rm, s->fast, s->stream);
+    });
 }
 
 template <typename T>
 hipError_t one_step(tf_solver* s, double dt, bool project_b) {
     const tf_grid& g = s->grid;
-    hipError_t e = forward_xy<T>(s);
+    hipError_t e = forward_xy<T>(s, TF_PASS_X_FORWARD, TF_PASS_Y_FORWARD);
     if (e != hipSuccess) return e;
     tf::StepParams p = step_params(s, dt, project_b);
-    e = tf::launch_z_pass<T>(s->spec, s->tw[2], p, tf::Z_STEP, nullptr, nullptr, s->stream);
+    e = timed(s, TF_PASS_Z_STEP, [&] {
+        return tf::launch_z_pass<T>(s->spec, s->tw[2], p, s->rm, tf::Z_STEP, nullptr, nullptr, nullptr, s->fast,
+                                    s->stream);
+    });
     if (e != hipSuccess) return e;
-    e = tf::launch_y_pass<T>(s->spec, s->tw[1], g.nx, g.ny, g.nz, +1, s->stream);
+    e = timed(s, TF_PASS_Y_INVERSE, [&] {
+        return tf::launch_y_pass<T>(s->spec, s->tw[1], g.nx, g.ny, g.nz, +1, s->rm, s->fast, s->stream);
+    });
     if (e != hipSuccess) return e;
-    return tf::launch_x_inverse<T>(s->spec, static_cast<T*>(s->state), s->tw[0], g.nx, g.ny, g.nz, s->stream);
+    return timed(s, TF_PASS_X_INVERSE, [&] {
+        return tf::launch_x_inverse<T>(s->spec, static_cast<T*>(s->state), s->tw[0], g.nx, g.ny, g.nz, s->rm,
+                                       s->stream);
+    });
 }
 
 hipError_t upload_twiddles(void* dst, int n, int prec, hipStream_t st) {
@@ -230,8 +271,10 @@ hipError_t upload_twiddles(void* dst, int n, int prec, hipStream_t st) {
 }
 
 void free_all(tf_solver* s) {
+    for (hipEvent_t ev : s->evpool) (void)hipEventDestroy(ev);
+    s->evpool.clear();
     void* ptrs[] = {s->state, s->spec, s->tw[0], s->tw[1], s->tw[2], s->partials, s->results,
-                    s->pulse_tab, s->scratch_out};
+                    s->pulse_tab, s->dcbuf, s->scratch_out};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -297,11 +340,20 @@ tf_status tf_create(const tf_grid* grid, int32_t precision, void* hip_stream, tf
     s->nkx = tf::nkx_of(grid->nx);
     const size_t state_b = 6 * (size_t)s->cells * s->esize;
     const size_t spec_b = (size_t)grid->nz * grid->ny * s->nkx * 6 * 2 * s->esize;
-    const int zb = precision == TF_F64 ? tf::z_pass_blocks<double>(grid->nx, grid->ny, grid->nz)
-                                       : tf::z_pass_blocks<float>(grid->nx, grid->ny, grid->nz);
+    const int zb = precision == TF_F64 ? tf::z_diag_blocks<double>(grid->nx, grid->ny, grid->nz)
+                                       : tf::z_diag_blocks<float>(grid->nx, grid->ny, grid->nz);
     s->npartials = std::max<size_t>(tf::SUMSQ_BLOCKS, (size_t)zb * 4);
     const size_t tw_b = 2 * s->esize * (size_t)(grid->nx + grid->ny + grid->nz);
-    const size_t need = state_b + spec_b + tw_b + s->npartials * 8 + 64;
+    const size_t dc_b = (size_t)grid->ny * grid->nz * 6 * 2 * s->esize;
+    const size_t need = state_b + spec_b + tw_b + dc_b + s->npartials * 8 + 64;
+    s->rm.ny = grid->ny;
+    s->rm.nz = grid->nz;
+    s->rm.G = 8;
+    if (const char* g = std::getenv("TFOCUS_ROW_BLOCK")) {
+        const int v = std::atoi(g);
+        if (v > 0 && grid->ny % v == 0) s->rm.G = v;
+    }
+    if (const char* f = std::getenv("TFOCUS_GENERIC_KERNELS")) s->fast = !(f[0] == '1');
     if (need > device_cap()) {
         delete s;
         return fail(TF_ENOMEM, "solver needs " + std::to_string(need) + " device bytes, above TFOCUS_MAX_DEVICE_BYTES");
@@ -319,6 +371,7 @@ tf_status tf_create(const tf_grid* grid, int32_t precision, void* hip_stream, tf
     for (int a = 0; a < 3 && st == TF_OK; ++a) st = alloc(&s->tw[a], 2 * s->esize * ns[a]);
     if (st == TF_OK) st = alloc((void**)&s->partials, s->npartials * sizeof(double));
     if (st == TF_OK) st = alloc((void**)&s->results, 8 * sizeof(double));
+    if (st == TF_OK) st = alloc(&s->dcbuf, dc_b);
     if (st != TF_OK) {
         free_all(s);
         delete s;
@@ -434,8 +487,10 @@ tf_status tf_set_pulse(tf_solver* s, const tf_pulse* pulse, tf_pulse_info* info)
         p.gnorm = gnorm;
     }
     tf::GridDev gd = grid_dev(s);
-    hipError_t e = s->prec == TF_F64 ? tf::launch_init_map<double>(static_cast<double*>(s->state), gd, p, s->stream)
-                                     : tf::launch_init_map<float>(static_cast<float*>(s->state), gd, p, s->stream);
+    hipError_t e = timed(s, TF_PASS_INIT, [&] {
+        return s->prec == TF_F64 ? tf::launch_init_map<double>(static_cast<double*>(s->state), gd, p, s->stream)
+                                 : tf::launch_init_map<float>(static_cast<float*>(s->state), gd, p, s->stream);
+    });
     if (e != hipSuccess) return fail(TF_EDEVICE, std::string("init kernel: ") + hipGetErrorString(e));
     s->t = 0.0;
     s->project_b_next = true;
@@ -498,11 +553,13 @@ tf_status tf_read_focal(tf_solver* s, const tf_window* w, void* dst, int32_t dst
         out = s->scratch_out;
     }
     tf::GridDev gd = grid_dev(s);
-    hipError_t e = s->prec == TF_F64
-                       ? tf::launch_readout<double>(static_cast<const double*>(s->state), static_cast<double*>(out), gd,
-                                                    w->wx, w->wy, w->wz, ic, jc, kc, s->t, s->R_min, s->R_max, s->stream)
-                       : tf::launch_readout<float>(static_cast<const float*>(s->state), static_cast<float*>(out), gd,
-                                                   w->wx, w->wy, w->wz, ic, jc, kc, s->t, s->R_min, s->R_max, s->stream);
+    hipError_t e = timed(s, TF_PASS_READOUT, [&] {
+        return s->prec == TF_F64
+                   ? tf::launch_readout<double>(static_cast<const double*>(s->state), static_cast<double*>(out), gd,
+                                                w->wx, w->wy, w->wz, ic, jc, kc, s->t, s->R_min, s->R_max, s->stream)
+                   : tf::launch_readout<float>(static_cast<const float*>(s->state), static_cast<float*>(out), gd,
+                                               w->wx, w->wy, w->wz, ic, jc, kc, s->t, s->R_min, s->R_max, s->stream);
+    });
     if (e != hipSuccess) return fail(TF_EDEVICE, std::string("readout kernel: ") + hipGetErrorString(e));
     if (!dst_on_device) {
         TF_HIP(hipMemcpyAsync(dst, out, bytes, hipMemcpyDeviceToHost, s->stream));
@@ -518,12 +575,16 @@ tf_status tf_diagnostics(tf_solver* s, double* energy, double* max_div_e, double
     e = s->prec == TF_F64 ? tf::launch_sumsq<double>(static_cast<const double*>(s->state), n, s->partials, tf::SUMSQ_BLOCKS, s->stream)
                           : tf::launch_sumsq<float>(static_cast<const float*>(s->state), n, s->partials, tf::SUMSQ_BLOCKS, s->stream);
     if (e == hipSuccess) e = tf::launch_reduce(s->partials, tf::SUMSQ_BLOCKS, 1, 0, 0, s->results, s->stream);
-    if (e == hipSuccess) e = s->prec == TF_F64 ? forward_xy<double>(s) : forward_xy<float>(s);
+    if (e == hipSuccess)
+        e = s->prec == TF_F64 ? forward_xy<double>(s, TF_PASS_OTHER, TF_PASS_OTHER)
+                              : forward_xy<float>(s, TF_PASS_OTHER, TF_PASS_OTHER);
     int nb = 0;
     if (e == hipSuccess) {
         tf::StepParams p = step_params(s, 0.0, false);
-        e = s->prec == TF_F64 ? tf::launch_z_pass<double>(s->spec, s->tw[2], p, tf::Z_DIAG, s->partials, &nb, s->stream)
-                              : tf::launch_z_pass<float>(s->spec, s->tw[2], p, tf::Z_DIAG, s->partials, &nb, s->stream);
+        e = s->prec == TF_F64 ? tf::launch_z_pass<double>(s->spec, s->tw[2], p, s->rm, tf::Z_DIAG, s->partials, s->dcbuf,
+                                                          &nb, s->fast, s->stream)
+                              : tf::launch_z_pass<float>(s->spec, s->tw[2], p, s->rm, tf::Z_DIAG, s->partials, s->dcbuf,
+                                                         &nb, s->fast, s->stream);
     }
     for (int q = 0; q < 4 && e == hipSuccess; ++q) e = tf::launch_reduce(s->partials, nb, 4, q, 1, s->results + 1 + q, s->stream);
     double h[5] = {0, 0, 0, 0, 0};
@@ -540,6 +601,34 @@ tf_status tf_diagnostics(tf_solver* s, double* energy, double* max_div_e, double
 tf_status tf_time(const tf_solver* s, double* t) {
     if (!s || !t) return fail(TF_EINVAL, "solver and t must not be NULL");
     *t = s->t;
+    return TF_OK;
+}
+
+tf_status tf_profile(tf_solver* s, int32_t enable) {
+    if (!s) return fail(TF_EINVAL, "solver is NULL");
+    if (enable) {
+        TF_HIP(hipStreamSynchronize(s->stream));
+        s->rec_kind.clear();
+    }
+    s->prof = enable != 0;
+    return TF_OK;
+}
+
+tf_status tf_profile_read(tf_solver* s, double* ms_total, int64_t* launches) {
+    if (!s) return fail(TF_EINVAL, "solver is NULL");
+    TF_HIP(hipStreamSynchronize(s->stream));
+    double ms[TF_NPASS] = {0};
+    int64_t cnt[TF_NPASS] = {0};
+    for (size_t i = 0; i < s->rec_kind.size(); ++i) {
+        float m = 0.0f;
+        TF_HIP(hipEventElapsedTime(&m, s->evpool[2 * i], s->evpool[2 * i + 1]));
+        ms[s->rec_kind[i]] += m;
+        cnt[s->rec_kind[i]] += 1;
+    }
+    for (int k = 0; k < TF_NPASS; ++k) {
+        if (ms_total) ms_total[k] = ms[k];
+        if (launches) launches[k] = cnt[k];
+    }
     return TF_OK;
 }
 

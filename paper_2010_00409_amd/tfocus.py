@@ -78,7 +78,11 @@ _SIGS = {
                         ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "tf_time": ([_P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "tf_get_grid": ([_P, ctypes.POINTER(tf_grid)], ctypes.c_int),
+    "tf_profile": ([_P, ctypes.c_int32], ctypes.c_int),
+    "tf_profile_read": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
 }
+
+PASS_NAMES = ("x_forward", "y_forward", "z_step", "y_inverse", "x_inverse", "init", "readout", "other")
 
 _lib = None
 
@@ -262,11 +266,25 @@ def tf_get_grid(h):
     return grid_dict(g)
 
 
+def tf_profile(h, enable):
+    _check(load().tf_profile(h, 1 if enable else 0))
+
+
+def tf_profile_read(h):
+    """{pass name: (total ms, launches)} since profiling was enabled."""
+    ms = (ctypes.c_double * len(PASS_NAMES))()
+    n = (ctypes.c_int64 * len(PASS_NAMES))()
+    _check(load().tf_profile_read(h, ms, n))
+    return {k: (ms[i], n[i]) for i, k in enumerate(PASS_NAMES)}
+
+
 class Solver:
-    """Owning wrapper of a tf_solver handle."""
+    """Owning wrapper of a tf_solver handle; checks buffer sizes and element
+    types before passing pointers to the library."""
 
     def __init__(self, grid, precision="f32", stream=None):
         self.precision = precision
+        self.itemsize = 8 if precision == "f64" else 4
         self.grid = grid_dict(grid_struct(grid))
         self.h = tf_create(grid, precision, stream)
 
@@ -292,10 +310,20 @@ class Solver:
         g = self.grid
         return (6, g["nz"], g["ny"], g["nx"])
 
+    def _expect(self, a, shape):
+        _, _, nbytes, item = _buffer(a)
+        n = 1
+        for v in shape:
+            n *= v
+        if item != self.itemsize or nbytes != n * self.itemsize:
+            raise ValueError(f"buffer must hold {shape} elements of {self.itemsize} bytes")
+
     def set_fields(self, src, t=0.0):
+        self._expect(src, self.shape)
         tf_set_fields(self.h, src, t)
 
     def get_fields(self, dst):
+        self._expect(dst, self.shape)
         return tf_get_fields(self.h, dst)
 
     def set_pulse(self, pulse):
@@ -308,7 +336,9 @@ class Solver:
         tf_advance(self.h, nsteps, dt)
 
     def read_focal(self, window, dst):
-        return tf_read_focal(self.h, window, dst)
+        w = window_struct(window)
+        self._expect(dst, (6, w.wz, w.wy, w.wx))
+        return tf_read_focal(self.h, w, dst)
 
     def diagnostics(self):
         return tf_diagnostics(self.h)
@@ -319,3 +349,9 @@ class Solver:
 
     def state_ptr(self):
         return tf_state_ptr(self.h)
+
+    def profile(self, enable=True):
+        tf_profile(self.h, enable)
+
+    def profile_read(self):
+        return tf_profile_read(self.h)

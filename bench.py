@@ -28,6 +28,9 @@ sys.path.insert(0, HERE)
 PEAK_HBM_GBS = 8000.0
 METRIC = "PSATD cell-updates/s + HBM GB/s at 512^3 FP32; surrogate speedup at 1e-2 err"
 PASS_BYTES_PER_CELL = {"f32": 48, "f64": 96}   # read + write of six components
+# kernel behind each pass of the float32 512^3 step (rocprofv3 short names)
+PASS_KERNEL = {"x_forward": "k_x_forward", "y_forward": "k_col_fast", "z_step": "k_z_fast",
+               "y_inverse": "k_col_fast", "x_inverse": "k_x_inverse"}
 
 
 def parse():
@@ -38,6 +41,8 @@ def parse():
     ap.add_argument("--psatd-steps", type=int, default=None, help="override steps per run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="c3", choices=["c3", "c2"])
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -48,7 +53,7 @@ def traffic_record(kernel):
     if not os.path.exists(path):
         return None
     import hashlib
-    rec = json.load(open(path)).get(kernel)
+    rec = json.load(open(path)).get(PASS_KERNEL.get(kernel, kernel))
     if not rec:
         return None
     src = os.path.join(HERE, "paper_2010_00409_amd", "csrc")
@@ -101,11 +106,15 @@ def main():
     out = torch.empty((6, win["wz"], win["wy"], win["wx"]), dtype=dtype, device="cuda")
     cells = n[0] * n[1] * n[2]
 
+    # the focal window is read when the pulse centre reaches the focus
+    focus_step = min(steps, int(round(cfg["pulse"]["R0"] / cfg["dt"])))
+
     with tf.Solver(grid, prec, stream) as s:
         def run():
             s.set_pulse(cfg["pulse"])
-            s.advance(steps, cfg["dt"])
+            s.advance(focus_step, cfg["dt"])
             s.read_focal(win, out)
+            s.advance(steps - focus_step, cfg["dt"])
 
         for _ in range(args.warmup):
             run()
@@ -120,6 +129,14 @@ def main():
         prof = s.profile_read()
         s.profile(False)
         peak_field = float(out.abs().max().item())
+
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     elapsed = t1 - t0
     cell_updates = cells * steps * args.steps
@@ -151,7 +168,8 @@ def main():
         "config": {
             "workload": (f"{cfg['name']}: {n[0]}^3 {prec} periodic layer, dx = lambda/{round(1 / cfg['spacing'][0])}, "
                          f"spectral pulse mapped into the layer, {steps} steps of dt = {cfg['dt']:.6g}, "
-                         f"64^3 focal window; one bench step = init + {steps} steps + readout"),
+                         f"64^3 focal window read at the focus (step {focus_step}); "
+                         f"one bench step = init + {steps} steps + readout"),
             "grid": list(n), "psatd_steps_per_run": steps, "precision": prec,
             "twiddles_and_phases": "float64-built",
         },

@@ -167,6 +167,7 @@ struct tf_solver {
     void* dcbuf = nullptr;         // diagnostics: packed kx = 0 slot after the forward z FFT
     tf::RowMap rm{};
     bool fast = true;              // use the specialised float32 column kernels
+    int zvariant = 0;
     void* scratch_out = nullptr;
     size_t scratch_bytes = 0;
     double t = 0.0;
@@ -199,6 +200,7 @@ tf::StepParams step_params(const tf_solver* s, double dt, bool project_b) {
     p.cdt = dt;
     p.scale = 1.0 / ((double)g.nx * (double)g.ny * (double)g.nz);
     p.project_b = project_b ? 1 : 0;
+    p.zvariant = s->zvariant;
     return p;
 }
 
@@ -354,6 +356,7 @@ tf_status tf_create(const tf_grid* grid, int32_t precision, void* hip_stream, tf
         if (v > 0 && grid->ny % v == 0) s->rm.G = v;
     }
     if (const char* f = std::getenv("TFOCUS_GENERIC_KERNELS")) s->fast = !(f[0] == '1');
+    if (const char* f = std::getenv("TFOCUS_ZVARIANT")) s->zvariant = std::atoi(f);
     if (need > device_cap()) {
         delete s;
         return fail(TF_ENOMEM, "solver needs " + std::to_string(need) + " device bytes, above TFOCUS_MAX_DEVICE_BYTES");

@@ -1,0 +1,176 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+bench times (256^3 and 512^3 float32, fast kernels, 8-row y blocks).
+
+Checks: pulse init + mapping at sampled nodes against the oracle; one step
+of the GPU state against the oracle's float64 step on the same float32
+input; many steps against the oracle's single exact jump (Sec. II.A: one
+step of any length is exact); closed-form plane waves at sampled nodes;
+energy and transversality; the focal window at the focus against the
+oracle's jump + cut-out."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mapping, psatd, pulse
+from paper_2010_00409_amd import tfocus as tf
+from synthetic import configs, planewaves
+
+pytestmark = pytest.mark.gpu
+
+F32_STEP_TOL = 1e-5
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def sample_nodes(grid, state, rng, nrand=4000, nsupport=4000):
+    """Random nodes plus nodes where the GPU init is non-zero."""
+    nz, ny, nx = grid["nz"], grid["ny"], grid["nx"]
+    idx = [rng.integers(0, n, nrand) for n in (nz, ny, nx)]
+    nzero = np.argwhere(np.abs(state[1]) + np.abs(state[0]) > 0)
+    if len(nzero):
+        pick = nzero[rng.integers(0, len(nzero), nsupport)]
+        idx = [np.concatenate([idx[a], pick[:, a]]) for a in range(3)]
+    return idx
+
+
+@pytest.fixture(scope="module")
+def c2_state():
+    """Raw init (for the init check) and the transverse state after the
+    first step's one-time removal of longitudinal B (dt = 0), for which n
+    steps of dt and one step of n dt agree."""
+    c = configs.c2()
+    grid = pulse.layer_grid(c["pulse"], c["n"], c["spacing"])
+    with tf.Solver(grid, "f32") as s:
+        s.set_pulse(c["pulse"])
+        init = np.empty(s.shape, np.float32)
+        s.get_fields(init)
+        s.advance(1, 0.0)
+        trans = np.empty(s.shape, np.float32)
+        s.get_fields(trans)
+    return c, grid, init, trans
+
+
+def test_C2_init_at_sampled_nodes(c2_state):
+    c, grid, init, _ = c2_state
+    iz, iy, ix = sample_nodes(grid, init, np.random.default_rng(0))
+    E, B = pulse.init_fields_at(c["pulse"], grid, iz, iy, ix)
+    ref = np.concatenate([E, B])
+    got = init[:, iz, iy, ix].astype(np.float64)
+    assert np.abs(ref).max() > 0.1
+    assert np.abs(got - ref).max() <= 2e-7 * np.abs(ref).max()
+
+
+def test_C2_one_step_and_jump_to_focus(c2_state):
+    c, grid, _, init = c2_state
+    sp = (grid["dz"], grid["dy"], grid["dx"])
+    x = init.astype(np.float64)
+    nfocus = int(round(c["pulse"]["R0"] / c["dt"]))
+    with tf.Solver(grid, "f32") as s:
+        s.set_fields(init)
+        s.advance(1, c["dt"])
+        one = np.empty(s.shape, np.float32)
+        s.get_fields(one)
+        s.set_fields(init)
+        s.set_cutout(c["pulse"]["R0"] - c["pulse"]["L"] / 2, c["pulse"]["R0"] + c["pulse"]["L"] / 2)
+        s.advance(nfocus, c["dt"])
+        win = c["window"]
+        wgpu = np.empty((6, win["wz"], win["wy"], win["wx"]), np.float32)
+        s.read_focal(win, wgpu)
+        t = s.t
+        full = np.empty(s.shape, np.float32)
+        s.get_fields(full)
+    Eo, Bo = psatd.step_fft(x[:3], x[3:], sp, c["dt"])
+    assert rel(one.astype(np.float64), np.concatenate([Eo, Bo])) <= F32_STEP_TOL
+    Ej, Bj = psatd.jump(x[:3], x[3:], sp, nfocus * c["dt"])
+    ref = np.concatenate([Ej, Bj])
+    # 400 float32 steps against one exact float64 jump: rounding accumulates
+    # as a random walk, ~ sqrt(400) x the per-step error
+    assert rel(full.astype(np.float64), ref) <= 20 * F32_STEP_TOL
+    geo = pulse.geometry(c["pulse"])
+    wref = mapping.readout(ref, grid, win, t, geo["R_min"], geo["R_max"])
+    assert np.abs(wref).max() > 1.0                      # the pulse is focused in the window
+    assert rel(wgpu.astype(np.float64), wref) <= 20 * F32_STEP_TOL
+
+
+def test_C3_fullsize_init_sampled_and_one_step():
+    c = configs.c3()
+    grid = pulse.layer_grid(c["pulse"], c["n"], c["spacing"])
+    sp = (grid["dz"], grid["dy"], grid["dx"])
+    with tf.Solver(grid, "f32") as s:
+        s.set_pulse(c["pulse"])
+        init = np.empty(s.shape, np.float32)
+        s.get_fields(init)
+        # one plain step from the raw init (set_fields clears the pending
+        # B projection, matching the oracle's step without it)
+        s.set_fields(init)
+        s.advance(1, c["dt"])
+        one = np.empty(s.shape, np.float32)
+        s.get_fields(one)
+    iz, iy, ix = sample_nodes(grid, init, np.random.default_rng(1))
+    E, B = pulse.init_fields_at(c["pulse"], grid, iz, iy, ix)
+    ref = np.concatenate([E, B])
+    assert np.abs(ref).max() > 0.1
+    assert np.abs(init[:, iz, iy, ix].astype(np.float64) - ref).max() <= 2e-7 * np.abs(ref).max()
+    x = init.astype(np.float64)
+    del init
+    Eo, Bo = psatd.step_fft(x[:3], x[3:], sp, c["dt"])
+    del x
+    assert rel(one.astype(np.float64), np.concatenate([Eo, Bo])) <= F32_STEP_TOL
+
+
+def test_C3_fullsize_planewaves_closed_form_and_invariants():
+    n = 512
+    g = configs.cube_grid(n, 1 / 12)
+    modes = planewaves.draw(33, nmodes=6, mmax=200)
+    E, B = planewaves.fields(modes, g, dtype=np.float32)
+    st = np.concatenate([E, B])
+    del E, B
+    dt, nst = 1 / 24, 5
+    with tf.Solver(g, "f32") as s:
+        s.set_fields(st)
+        e0, _, _ = s.diagnostics()
+        s.advance(nst, dt)
+        e1, de, db = s.diagnostics()
+        out = np.empty(s.shape, np.float32)
+        s.get_fields(out)
+    assert e1 == pytest.approx(e0, rel=1e-5)
+    assert de < 1e-5 and db < 1e-5
+    rng = np.random.default_rng(2)
+    iz, iy, ix = (rng.integers(0, n, 20000) for _ in range(3))
+    x = g["x_min"] + ix * g["dx"]
+    y = g["y_min"] + iy * g["dy"]
+    z = g["z_min"] + iz * g["dz"]
+    t = nst * dt
+    ref = np.zeros((6, len(ix)))
+    for md in modes:
+        k = planewaves.kvec(md, g)
+        w = math.sqrt(k @ k)
+        c = md["amp"] * np.cos(k[0] * x + k[1] * y + k[2] * z - md["sign"] * w * t + md["phase"])
+        b = md["sign"] * np.cross(k / w, md["e"])
+        for a in range(3):
+            ref[a] += md["e"][a] * c
+            ref[3 + a] += b[a] * c
+    got = out[:, iz, iy, ix].astype(np.float64)
+    assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max() * 10
+
+
+def test_edge_cases_zero_steps_zero_dt_and_negative_dt():
+    g = configs.cube_grid(64, 0.25)
+    x = np.random.default_rng(4).standard_normal((6, 64, 64, 64)).astype(np.float32)
+    with tf.Solver(g, "f32") as s:
+        s.set_fields(x, 2.0)
+        s.advance(0, 0.3)
+        out = np.empty(s.shape, np.float32)
+        s.get_fields(out)
+        assert np.array_equal(out, x) and s.t == 2.0
+        s.advance(1, 0.0)                      # pure projection of E
+        s.get_fields(out)
+        Eo, Bo = psatd.step_fft(x[:3].astype(np.float64), x[3:].astype(np.float64), (0.25,) * 3, 0.0)
+        assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= F32_STEP_TOL
+        s.advance(3, -0.7)
+        assert s.t == pytest.approx(2.0 - 2.1)
+    with pytest.raises(tf.TfError):
+        tf.tf_advance(tf.Solver(g, "f32").h, -1, 0.1)

@@ -227,6 +227,47 @@ tf_status tf_profile(tf_solver* s, int32_t enable);
  * array (TF_NPASS entries) may be NULL. */
 tf_status tf_profile_read(tf_solver* s, double* ms_total, int64_t* launches);
 
+/* ---- batched sweeps (uneven grids) ------------------------------------- */
+
+typedef struct tf_batch tf_batch;
+
+/* n independent instances (grid + pulse), precision for all.  Instances with
+ * identical grids share one allocation and run together: every pass of a
+ * step is one launch over all active instances of that grid.  Validates
+ * every grid and pulse (TF_EDOMAIN if an instance's D <= L) and uploads the
+ * pulse tables; the states are initialised by tf_batch_run. */
+tf_status tf_batch_create(const tf_grid* grids, const tf_pulse* pulses, int32_t n, int32_t precision,
+                          void* hip_stream, tf_batch** out);
+
+/* One sweep: initialise every instance from its pulse (as tf_set_pulse),
+ * advance instance i by nsteps[i] steps of dt[i] (the first step removes
+ * longitudinal B once, as after tf_set_pulse), and cut out the window
+ * (shared shape and centre, Eqs. (14)-(16) at t_i = nsteps[i] dt[i]) into
+ * dst_dev + i * 6 * wx * wy * wz (device memory, n windows, solver element
+ * type).  use_graph = 1 captures the whole sweep into a hipGraph on first
+ * use and replays it while nsteps, dt, the window and dst_dev are unchanged;
+ * 0 launches eagerly.  Asynchronous on the batch stream. */
+tf_status tf_batch_run(tf_batch* b, const int64_t* nsteps, const double* dt, const tf_window* win,
+                       void* dst_dev, int32_t use_graph);
+
+/* Final state [6][nz][ny][nx] of instance i after the last run. */
+tf_status tf_batch_get_fields(tf_batch* b, int32_t i, void* dst, int32_t dst_on_device);
+
+tf_status tf_batch_destroy(tf_batch* b);
+
+/* ---- kernel plans and the autotuner ------------------------------------ */
+
+/* Plan file consulted by tf_create and tf_batch_create (also taken from the
+ * environment variable TFOCUS_PLAN_FILE).  NULL or "" clears it. */
+tf_status tf_set_plan_file(const char* path);
+
+/* For each cube size N in sizes[0..n): time a few steps of every kernel
+ * plan (y row blocking 8 or none; generic kernels or the fast float32
+ * kernels with each z strip shape) on the current device with HIP events,
+ * keep the fastest, and merge "arch precision N N N row_block fast zvariant
+ * ms" into plan_path.  best_ms (nullable) receives the best ms per step. */
+tf_status tf_tune(const int32_t* sizes, int32_t n, int32_t precision, const char* plan_path, double* best_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,11 +2,11 @@
 #include "fft_passes.inc"
 
 namespace tf {
-template hipError_t launch_x_forward<float>(const float*, void*, const void*, int, int, int, RowMap, hipStream_t);
-template hipError_t launch_x_inverse<float>(const void*, float*, const void*, int, int, int, RowMap, hipStream_t);
-template hipError_t launch_y_pass<float>(void*, const void*, int, int, int, int, RowMap, bool, hipStream_t);
+template hipError_t launch_x_forward<float>(const float*, void*, const void*, int, int, int, RowMap, Batch, hipStream_t);
+template hipError_t launch_x_inverse<float>(const void*, float*, const void*, int, int, int, RowMap, Batch, hipStream_t);
+template hipError_t launch_y_pass<float>(void*, const void*, int, int, int, int, RowMap, bool, Batch, hipStream_t);
 template hipError_t launch_z_pass<float>(void*, const void*, const StepParams&, RowMap, int, double*, void*, int*, bool,
-                                       hipStream_t);
+                                       Batch, hipStream_t);
 template int z_diag_blocks<float>(int, int, int);
 }  // namespace tf
 

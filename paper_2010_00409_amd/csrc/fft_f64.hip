@@ -2,10 +2,10 @@
 #include "fft_passes.inc"
 
 namespace tf {
-template hipError_t launch_x_forward<double>(const double*, void*, const void*, int, int, int, RowMap, hipStream_t);
-template hipError_t launch_x_inverse<double>(const void*, double*, const void*, int, int, int, RowMap, hipStream_t);
-template hipError_t launch_y_pass<double>(void*, const void*, int, int, int, int, RowMap, bool, hipStream_t);
+template hipError_t launch_x_forward<double>(const double*, void*, const void*, int, int, int, RowMap, Batch, hipStream_t);
+template hipError_t launch_x_inverse<double>(const void*, double*, const void*, int, int, int, RowMap, Batch, hipStream_t);
+template hipError_t launch_y_pass<double>(void*, const void*, int, int, int, int, RowMap, bool, Batch, hipStream_t);
 template hipError_t launch_z_pass<double>(void*, const void*, const StepParams&, RowMap, int, double*, void*, int*, bool,
-                                       hipStream_t);
+                                       Batch, hipStream_t);
 template int z_diag_blocks<double>(int, int, int);
 }  // namespace tf

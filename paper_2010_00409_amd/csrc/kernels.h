@@ -30,16 +30,26 @@ struct StepParams {
 
 enum ZMode { Z_STEP = 0, Z_DIAG = 1 };
 
+// Launch over n same-shape instances (grid y): instance i's state and
+// spectrum start sreal resp. sspec elements (of the element type resp.
+// complex) after instance 0's; cdt (nullable, n values on the device)
+// overrides StepParams::cdt per instance.
+struct Batch {
+    int n = 1;
+    long sreal = 0, sspec = 0;
+    const double* cdt = nullptr;
+};
+
 // Forward x pass: real state [6][nz][ny][nx] -> spectral (x transformed).
 template <typename T> hipError_t launch_x_forward(const T* real, void* spec, const void* tw,
-                                                  int nx, int ny, int nz, RowMap rm, hipStream_t st);
+                                                  int nx, int ny, int nz, RowMap rm, Batch bt, hipStream_t st);
 // Inverse x pass: spectral -> real state.
 template <typename T> hipError_t launch_x_inverse(const void* spec, T* real, const void* tw,
-                                                  int nx, int ny, int nz, RowMap rm, hipStream_t st);
+                                                  int nx, int ny, int nz, RowMap rm, Batch bt, hipStream_t st);
 // In-place y transform of the spectral array, dir = -1 forward, +1 inverse.
 // fast = false forces the generic kernels.
 template <typename T> hipError_t launch_y_pass(void* spec, const void* tw, int nx, int ny, int nz,
-                                               int dir, RowMap rm, bool fast, hipStream_t st);
+                                               int dir, RowMap rm, bool fast, Batch bt, hipStream_t st);
 // z pass: Z_STEP = forward z FFT, Eqs. (3)-(4) update, inverse z FFT, in place;
 // Z_DIAG = forward z FFT and per-block maxima |k.E|, |k.B|, |E|, |B| into
 // partials (4 doubles per block; the packed kx = 0 slot goes through dc, a
@@ -47,7 +57,7 @@ template <typename T> hipError_t launch_y_pass(void* spec, const void* tw, int n
 // number of 4-wide partials written.
 template <typename T> hipError_t launch_z_pass(void* spec, const void* tw, const StepParams& p,
                                                RowMap rm, int mode, double* partials, void* dc,
-                                               int* nblocks, bool fast, hipStream_t st);
+                                               int* nblocks, bool fast, Batch bt, hipStream_t st);
 template <typename T> int z_diag_blocks(int nx, int ny, int nz);
 
 // Twiddle tables are per axis length: tw[e] = exp(-2 pi i e / n).

@@ -1,5 +1,6 @@
-// Host engine behind the C ABI of include/tfocus.h: argument validation,
-// pulse geometry, twiddle tables, buffers and the step driver.
+// Host engine behind the single-grid part of the C ABI (include/tfocus.h):
+// buffers, pulse initialisation, the step driver, cut-out, diagnostics and
+// per-launch profiling.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -10,145 +11,17 @@
 #include <string>
 #include <vector>
 
-#include "../../include/tfocus.h"
-#include "kernels.h"
+#include "engine.h"
+
 
 namespace {
-
-thread_local std::string g_last_error;
-
-tf_status fail(tf_status st, const std::string& msg) {
-    g_last_error = msg;
-    return st;
-}
-
-#define TF_HIP(call)                                                                          \
-    do {                                                                                      \
-        hipError_t e_ = (call);                                                               \
-        if (e_ != hipSuccess)                                                                 \
-            return fail(TF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));       \
-    } while (0)
-
-bool length_ok(int n) {
-    if (n < 8 || n > 1024) return false;
-    int m = n;
-    while (m % 2 == 0) m /= 2;
-    while (m % 3 == 0) m /= 3;
-    return m == 1 && tf::fft_length_supported(n);
-}
-
-bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
-
-// ---- pulse geometry (host, float64) ----
-
-// F(theta0) = int_0^pi sin(a) exp(-2 a^2 / theta0^2) da by composite Simpson
-// on [0, min(pi, 12 theta0)] (the integrand is below e^-288 beyond).
-double F_gauss(double t0) {
-    const double b = std::fmin(M_PI, 12.0 * t0);
-    const int n = 1 << 20;
-    const double h = b / n;
-    auto f = [&](double a) { return std::sin(a) * std::exp(-2.0 * a * a / (t0 * t0)); };
-    double s = f(0.0) + f(b);
-    for (int i = 1; i < n; ++i) s += (i & 1 ? 4.0 : 2.0) * f(i * h);
-    return s * h / 3.0;
-}
-
-tf_status validate_pulse(const tf_pulse* p) {
-    if (!p) return fail(TF_EINVAL, "pulse is NULL");
-    if (p->envelope < 0 || p->envelope > 2) return fail(TF_EINVAL, "unknown envelope");
-    if (p->transverse < 0 || p->transverse > 1) return fail(TF_EINVAL, "unknown transverse profile");
-    if (p->polarization < 0 || p->polarization > 1) return fail(TF_EINVAL, "unknown polarization");
-    if (!finite_pos(p->wavelength)) return fail(TF_EINVAL, "wavelength must be > 0");
-    if (!finite_pos(p->L)) return fail(TF_EINVAL, "L must be > 0");
-    if (!finite_pos(p->R0) || !(p->R0 - 0.5 * p->L > 0.0)) return fail(TF_EINVAL, "need R0 > L/2 > 0");
-    if (!(p->theta > 0.0) && !finite_pos(p->f_number)) return fail(TF_EINVAL, "need theta > 0 or f_number > 0");
-    if (p->theta > 0.0 && !(p->theta < M_PI)) return fail(TF_EINVAL, "theta must be < pi");
-    if (p->transverse == TF_TS_FLATTOP && !finite_pos(p->eps)) return fail(TF_EINVAL, "eps must be > 0");
-    if (!std::isfinite(p->P0) || p->P0 < 0.0) return fail(TF_EINVAL, "P0 must be >= 0");
-    if (p->envelope == TF_ENV_GAUSS && !finite_pos(p->ncycles)) return fail(TF_EINVAL, "ncycles must be > 0");
-    if (p->envelope == TF_ENV_SPECTRAL) {
-        if (p->nfreq < 1 || p->nfreq > 4096) return fail(TF_EINVAL, "nfreq must be in [1, 4096]");
-        if (!finite_pos(p->bandwidth)) return fail(TF_EINVAL, "bandwidth must be > 0");
-        if (!std::isfinite(p->gdd) || !std::isfinite(p->tod)) return fail(TF_EINVAL, "chirp must be finite");
-    }
-    if (!std::isfinite(p->cep) || !std::isfinite(p->pol_angle) || !std::isfinite(p->ellipticity))
-        return fail(TF_EINVAL, "phase/polarisation parameters must be finite");
-    if (p->polarization == TF_POL_RADIAL && p->ellipticity != 0.0)
-        return fail(TF_EINVAL, "radial polarisation takes no ellipticity");
-    return TF_OK;
-}
-
-double theta_of(const tf_pulse* p) {
-    return p->theta > 0.0 ? p->theta : std::atan(1.0 / (2.0 * p->f_number));
-}
-
-void geometry(const tf_pulse* p, tf_pulse_info* g) {
-    std::memset(g, 0, sizeof(*g));
-    const double th = theta_of(p);
-    g->theta = th;
-    g->L = p->L;
-    g->R_min = p->R0 - 0.5 * p->L;
-    g->R_max = p->R0 + 0.5 * p->L;
-    if (p->transverse == TF_TS_FLATTOP) {
-        g->A = std::sqrt(4.0 * p->P0 / (1.0 - std::cos(th)));
-        g->alpha_max = th + 0.5 * p->eps;
-    } else {
-        g->A = std::sqrt(4.0 * p->P0 / F_gauss(th));
-        g->alpha_max = 0.5 * M_PI;
-    }
-    const double s = std::sin(th);
-    g->D_min = -g->R_min * std::cos(th) + std::sqrt(g->R_max * g->R_max - g->R_min * g->R_min * s * s);
-}
-
-// Spectral samples {w, a, phi} of the sampled Gaussian spectrum and the
-// normalisation max |g| over zeta_j = j lambda / 128 inside the window.
-void spectral_table(const tf_pulse* p, std::vector<double>& tab, double& gnorm) {
-    const int M = p->nfreq;
-    const double w0 = 2.0 * M_PI / p->wavelength;
-    const double dl = p->bandwidth;
-    const double X = 4.0;
-    tab.clear();
-    for (int m = 0; m < M; ++m) {
-        const double x = -X + (m + 0.5) * (2.0 * X / M);
-        const double w = w0 * (1.0 + dl * x);
-        if (!(w > 0.0)) continue;
-        const double u = (w - w0) / (dl * w0), v = (w + w0) / (dl * w0);
-        const double a = std::exp(-(u * u)) - std::exp(-(v * v));
-        const double dw = w - w0;
-        const double phi = p->gdd * dw * dw / 2.0 + p->tod * dw * dw * dw / 6.0;
-        tab.push_back(w);
-        tab.push_back(a);
-        tab.push_back(phi);
-    }
-    const double h = p->wavelength / 128.0;
-    const long jmax = (long)std::floor(0.5 * p->L / h);
-    gnorm = 0.0;
-    const int K = (int)(tab.size() / 3);
-    for (long j = -jmax; j <= jmax; ++j) {
-        const double z = j * h;
-        double acc = 0.0;
-        for (int m = 0; m < K; ++m) acc += tab[3 * m + 1] * std::cos(p->cep + 0.5 * M_PI + tab[3 * m + 2] - tab[3 * m] * z);
-        gnorm = std::fmax(gnorm, std::fabs(acc));
-    }
-}
-
-std::vector<double> twiddle_table(int n) {
-    std::vector<double> t(2 * n);
-    for (int e = 0; e < n; ++e) {
-        const double a = 2.0 * M_PI * (double)e / (double)n;
-        t[2 * e] = std::cos(a);
-        t[2 * e + 1] = -std::sin(a);
-    }
-    return t;
-}
-
-size_t device_cap() {
-    const char* s = std::getenv("TFOCUS_MAX_DEVICE_BYTES");
-    if (!s || !*s) return (size_t)-1;
-    return (size_t)std::strtoull(s, nullptr, 10);
-}
-
+using namespace tf::host;
 }  // namespace
+
+std::string& tf::host::last_error() {
+    static thread_local std::string e;
+    return e;
+}
 
 struct tf_solver {
     tf_grid grid{};
@@ -182,28 +55,6 @@ struct tf_solver {
 
 namespace {
 
-tf::GridDev grid_dev(const tf_solver* s) {
-    tf::GridDev g;
-    g.nx = s->grid.nx; g.ny = s->grid.ny; g.nz = s->grid.nz;
-    g.dx = s->grid.dx; g.dy = s->grid.dy; g.dz = s->grid.dz;
-    g.x_min = s->grid.x_min; g.y_min = s->grid.y_min; g.z_min = s->grid.z_min;
-    return g;
-}
-
-tf::StepParams step_params(const tf_solver* s, double dt, bool project_b) {
-    tf::StepParams p;
-    const tf_grid& g = s->grid;
-    p.nx = g.nx; p.ny = g.ny; p.nz = g.nz; p.nkx = s->nkx;
-    p.kfx = 2.0 * M_PI / (g.nx * g.dx);
-    p.kfy = 2.0 * M_PI / (g.ny * g.dy);
-    p.kfz = 2.0 * M_PI / (g.nz * g.dz);
-    p.cdt = dt;
-    p.scale = 1.0 / ((double)g.nx * (double)g.ny * (double)g.nz);
-    p.project_b = project_b ? 1 : 0;
-    p.zvariant = s->zvariant;
-    return p;
-}
-
 // Runs launch() and, while profiling, brackets it with a pair of events.
 template <class F>
 hipError_t timed(tf_solver* s, int kind, F launch) {
@@ -229,11 +80,11 @@ hipError_t forward_xy(tf_solver* s, int kind_x, int kind_y) {
     const tf_grid& g = s->grid;
     hipError_t e = timed(s, kind_x, [&] {
         return tf::launch_x_forward<T>(static_cast<const T*>(s->state), s->spec, s->tw[0], g.nx, g.ny, g.nz, s->rm,
-                                       s->stream);
+                                       tf::Batch{}, s->stream);
     });
     if (e != hipSuccess) return e;
     return timed(s, kind_y, [&] {
-        return tf::launch_y_pass<T>(s->spec, s->tw[1], g.nx, g.ny, g.nz, -1, s->rm, s->fast, s->stream);
+        return tf::launch_y_pass<T>(s->spec, s->tw[1], g.nx, g.ny, g.nz, -1, s->rm, s->fast, tf::Batch{}, s->stream);
     });
 }
 
@@ -242,34 +93,20 @@ hipError_t one_step(tf_solver* s, double dt, bool project_b) {
     const tf_grid& g = s->grid;
     hipError_t e = forward_xy<T>(s, TF_PASS_X_FORWARD, TF_PASS_Y_FORWARD);
     if (e != hipSuccess) return e;
-    tf::StepParams p = step_params(s, dt, project_b);
+    tf::StepParams p = step_params(s->grid, dt, project_b, s->zvariant);
     e = timed(s, TF_PASS_Z_STEP, [&] {
         return tf::launch_z_pass<T>(s->spec, s->tw[2], p, s->rm, tf::Z_STEP, nullptr, nullptr, nullptr, s->fast,
-                                    s->stream);
+                                    tf::Batch{}, s->stream);
     });
     if (e != hipSuccess) return e;
     e = timed(s, TF_PASS_Y_INVERSE, [&] {
-        return tf::launch_y_pass<T>(s->spec, s->tw[1], g.nx, g.ny, g.nz, +1, s->rm, s->fast, s->stream);
+        return tf::launch_y_pass<T>(s->spec, s->tw[1], g.nx, g.ny, g.nz, +1, s->rm, s->fast, tf::Batch{}, s->stream);
     });
     if (e != hipSuccess) return e;
     return timed(s, TF_PASS_X_INVERSE, [&] {
         return tf::launch_x_inverse<T>(s->spec, static_cast<T*>(s->state), s->tw[0], g.nx, g.ny, g.nz, s->rm,
-                                       s->stream);
+                                       tf::Batch{}, s->stream);
     });
-}
-
-hipError_t upload_twiddles(void* dst, int n, int prec, hipStream_t st) {
-    std::vector<double> t = twiddle_table(n);
-    if (prec == TF_F64) {
-        hipError_t e = hipMemcpyAsync(dst, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) return e;
-        return hipStreamSynchronize(st);
-    }
-    std::vector<float> f(t.size());
-    for (size_t i = 0; i < t.size(); ++i) f[i] = (float)t[i];
-    hipError_t e = hipMemcpyAsync(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return e;
-    return hipStreamSynchronize(st);
 }
 
 void free_all(tf_solver* s) {
@@ -287,7 +124,7 @@ extern "C" {
 
 const char* tf_version(void) { return "tfocus 0.1"; }
 
-const char* tf_last_error(void) { return g_last_error.c_str(); }
+const char* tf_last_error(void) { return last_error().c_str(); }
 
 int32_t tf_supported_length(int32_t n) { return length_ok(n) ? 1 : 0; }
 
@@ -323,16 +160,10 @@ tf_status tf_create(const tf_grid* grid, int32_t precision, void* hip_stream, tf
     if (!grid || !out) return fail(TF_EINVAL, "grid and out must not be NULL");
     *out = nullptr;
     if (precision != TF_F32 && precision != TF_F64) return fail(TF_EINVAL, "precision must be TF_F32 or TF_F64");
-    if (grid->nx % 2 != 0) return fail(TF_EINVAL, "nx must be even");
-    if (grid->nx <= 0 || grid->ny <= 0 || grid->nz <= 0) return fail(TF_EINVAL, "grid sizes must be > 0");
-    if (!finite_pos(grid->dx) || !finite_pos(grid->dy) || !finite_pos(grid->dz))
-        return fail(TF_EINVAL, "spacings must be finite and > 0");
-    if (!std::isfinite(grid->x_min) || !std::isfinite(grid->y_min) || !std::isfinite(grid->z_min))
-        return fail(TF_EINVAL, "grid origin must be finite");
-    for (int n : {grid->nx, grid->ny, grid->nz})
-        if (!length_ok(n))
-            return fail(TF_EUNSUPPORTED, "axis length " + std::to_string(n) +
-                                             " unsupported (products of 2 and 3, 8..1024)");
+    {
+        tf_status vs = validate_grid(grid);
+        if (vs != TF_OK) return vs;
+    }
     tf_solver* s = new tf_solver();
     s->grid = *grid;
     s->prec = precision;
@@ -348,15 +179,12 @@ tf_status tf_create(const tf_grid* grid, int32_t precision, void* hip_stream, tf
     const size_t tw_b = 2 * s->esize * (size_t)(grid->nx + grid->ny + grid->nz);
     const size_t dc_b = (size_t)grid->ny * grid->nz * 6 * 2 * s->esize;
     const size_t need = state_b + spec_b + tw_b + dc_b + s->npartials * 8 + 64;
+    const KernelPlan kp = plan_for(*grid, precision);
     s->rm.ny = grid->ny;
     s->rm.nz = grid->nz;
-    s->rm.G = 8;
-    if (const char* g = std::getenv("TFOCUS_ROW_BLOCK")) {
-        const int v = std::atoi(g);
-        if (v > 0 && grid->ny % v == 0) s->rm.G = v;
-    }
-    if (const char* f = std::getenv("TFOCUS_GENERIC_KERNELS")) s->fast = !(f[0] == '1');
-    if (const char* f = std::getenv("TFOCUS_ZVARIANT")) s->zvariant = std::atoi(f);
+    s->rm.G = kp.row_block;
+    s->fast = kp.fast;
+    s->zvariant = kp.zvariant;
     if (need > device_cap()) {
         delete s;
         return fail(TF_ENOMEM, "solver needs " + std::to_string(need) + " device bytes, above TFOCUS_MAX_DEVICE_BYTES");
@@ -440,37 +268,7 @@ tf_status tf_set_pulse(tf_solver* s, const tf_pulse* pulse, tf_pulse_info* info)
     if (info) *info = g;
     if (!(g.D > pulse->L)) return fail(TF_EDOMAIN, "layer period D = nx dx must exceed the pulse length L");
 
-    tf::PulseDev p{};
-    p.envelope = pulse->envelope;
-    p.transverse = pulse->transverse;
-    p.polarization = pulse->polarization;
-    p.lambda = pulse->wavelength;
-    p.R0 = pulse->R0;
-    p.L = pulse->L;
-    p.ncycles = pulse->ncycles;
-    p.theta = g.theta;
-    p.eps = pulse->eps;
-    p.A = g.A;
-    p.alpha_max = g.alpha_max;
-    p.cep = pulse->cep;
-    p.gnorm = 1.0;
-    if (pulse->polarization == TF_POL_RADIAL) {
-        p.nparts = 1;
-        p.amp[0] = 1.0;
-        p.d[0][0] = 1.0; p.d[0][1] = 0.0; p.d[0][2] = 0.0;
-        p.phase_off[0] = 0.0;
-    } else {
-        const double c = std::cos(pulse->pol_angle), sn = std::sin(pulse->pol_angle);
-        const double e = pulse->ellipticity;
-        const double nrm = std::sqrt(1.0 + e * e);
-        p.nparts = e != 0.0 ? 2 : 1;
-        p.amp[0] = 1.0 / nrm;
-        p.d[0][0] = 0.0; p.d[0][1] = c; p.d[0][2] = sn;
-        p.phase_off[0] = 0.0;
-        p.amp[1] = e / nrm;
-        p.d[1][0] = 0.0; p.d[1][1] = -sn; p.d[1][2] = c;
-        p.phase_off[1] = 0.5 * M_PI;
-    }
+    tf::PulseDev p = pulse_dev(pulse, g);
     if (pulse->envelope == TF_ENV_SPECTRAL) {
         std::vector<double> tab;
         double gnorm = 0.0;
@@ -489,7 +287,7 @@ tf_status tf_set_pulse(tf_solver* s, const tf_pulse* pulse, tf_pulse_info* info)
         p.spec = static_cast<const double*>(s->pulse_tab);
         p.gnorm = gnorm;
     }
-    tf::GridDev gd = grid_dev(s);
+    tf::GridDev gd = grid_dev(s->grid);
     hipError_t e = timed(s, TF_PASS_INIT, [&] {
         return s->prec == TF_F64 ? tf::launch_init_map<double>(static_cast<double*>(s->state), gd, p, s->stream)
                                  : tf::launch_init_map<float>(static_cast<float*>(s->state), gd, p, s->stream);
@@ -555,7 +353,7 @@ tf_status tf_read_focal(tf_solver* s, const tf_window* w, void* dst, int32_t dst
         }
         out = s->scratch_out;
     }
-    tf::GridDev gd = grid_dev(s);
+    tf::GridDev gd = grid_dev(s->grid);
     hipError_t e = timed(s, TF_PASS_READOUT, [&] {
         return s->prec == TF_F64
                    ? tf::launch_readout<double>(static_cast<const double*>(s->state), static_cast<double*>(out), gd,
@@ -583,11 +381,11 @@ tf_status tf_diagnostics(tf_solver* s, double* energy, double* max_div_e, double
                               : forward_xy<float>(s, TF_PASS_OTHER, TF_PASS_OTHER);
     int nb = 0;
     if (e == hipSuccess) {
-        tf::StepParams p = step_params(s, 0.0, false);
+        tf::StepParams p = step_params(s->grid, 0.0, false, s->zvariant);
         e = s->prec == TF_F64 ? tf::launch_z_pass<double>(s->spec, s->tw[2], p, s->rm, tf::Z_DIAG, s->partials, s->dcbuf,
-                                                          &nb, s->fast, s->stream)
+                                                          &nb, s->fast, tf::Batch{}, s->stream)
                               : tf::launch_z_pass<float>(s->spec, s->tw[2], p, s->rm, tf::Z_DIAG, s->partials, s->dcbuf,
-                                                         &nb, s->fast, s->stream);
+                                                         &nb, s->fast, tf::Batch{}, s->stream);
     }
     for (int q = 0; q < 4 && e == hipSuccess; ++q) e = tf::launch_reduce(s->partials, nb, 4, q, 1, s->results + 1 + q, s->stream);
     double h[5] = {0, 0, 0, 0, 0};

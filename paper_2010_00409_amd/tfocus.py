@@ -78,6 +78,15 @@ _SIGS = {
                         ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "tf_time": ([_P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "tf_get_grid": ([_P, ctypes.POINTER(tf_grid)], ctypes.c_int),
+    "tf_batch_create": ([ctypes.POINTER(tf_grid), ctypes.POINTER(tf_pulse), ctypes.c_int32, ctypes.c_int32, _P,
+                         ctypes.POINTER(_P)], ctypes.c_int),
+    "tf_batch_run": ([_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(tf_window),
+                      _P, ctypes.c_int32], ctypes.c_int),
+    "tf_batch_get_fields": ([_P, ctypes.c_int32, _P, ctypes.c_int32], ctypes.c_int),
+    "tf_batch_destroy": ([_P], ctypes.c_int),
+    "tf_set_plan_file": ([ctypes.c_char_p], ctypes.c_int),
+    "tf_tune": ([ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p,
+                 ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "tf_profile": ([_P, ctypes.c_int32], ctypes.c_int),
     "tf_profile_read": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
 }
@@ -276,6 +285,78 @@ def tf_profile_read(h):
     n = (ctypes.c_int64 * len(PASS_NAMES))()
     _check(load().tf_profile_read(h, ms, n))
     return {k: (ms[i], n[i]) for i, k in enumerate(PASS_NAMES)}
+
+
+def tf_set_plan_file(path):
+    _check(load().tf_set_plan_file(path.encode() if path else None))
+
+
+def tf_tune(sizes, precision, plan_path):
+    """Tune the kernel plans of the cube sizes; returns best ms per step."""
+    arr = (ctypes.c_int32 * len(sizes))(*sizes)
+    best = (ctypes.c_double * len(sizes))()
+    prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    _check(load().tf_tune(arr, len(sizes), prec, plan_path.encode(), best))
+    return list(best)
+
+
+class Batch:
+    """Owning wrapper of a tf_batch (uneven-grid parameter sweep)."""
+
+    def __init__(self, grids, pulses, precision="f32", stream=None):
+        if len(grids) != len(pulses) or not grids:
+            raise ValueError("need equal, non-empty lists of grids and pulses")
+        self.n = len(grids)
+        self.precision = precision
+        self.itemsize = 8 if precision == "f64" else 4
+        self.grids = [grid_dict(grid_struct(g)) for g in grids]
+        G = (tf_grid * self.n)(*[grid_struct(g) for g in grids])
+        P = (tf_pulse * self.n)(*[pulse_struct(p) for p in pulses])
+        h = ctypes.c_void_p()
+        prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
+        _check(load().tf_batch_create(G, P, self.n, prec, _stream_ptr(stream), ctypes.byref(h)))
+        self.h = h
+        self._ran = False
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            _check(load().tf_batch_destroy(self.h))
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, nsteps, dt, window, dst, use_graph=True):
+        """dst: device tensor holding n x 6 x wz x wy x wx elements."""
+        if len(nsteps) != self.n or len(dt) != self.n:
+            raise ValueError("need one nsteps and one dt per instance")
+        w = window_struct(window)
+        ptr, dev, nbytes, item = _buffer(dst)
+        if not dev:
+            raise ValueError("batch windows are written to device memory")
+        if item != self.itemsize or nbytes != self.n * 6 * w.wx * w.wy * w.wz * item:
+            raise ValueError("dst must hold n x 6 x wz x wy x wx elements of the batch precision")
+        ns = (ctypes.c_int64 * self.n)(*[int(v) for v in nsteps])
+        ds = (ctypes.c_double * self.n)(*[float(v) for v in dt])
+        _check(load().tf_batch_run(self.h, ns, ds, ctypes.byref(w), ptr, 1 if use_graph else 0))
+        self._ran = True
+
+    def get_fields(self, i, dst):
+        g = self.grids[i]
+        ptr, dev, nbytes, item = _buffer(dst)
+        if item != self.itemsize or nbytes != 6 * g["nx"] * g["ny"] * g["nz"] * item:
+            raise ValueError("dst must hold the instance state")
+        _check(load().tf_batch_get_fields(self.h, int(i), ptr, dev))
+        return dst
 
 
 class Solver:

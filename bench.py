@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1, help="untimed runs")
     ap.add_argument("--psatd-steps", type=int, default=None, help="override steps per run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4"])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -84,12 +84,59 @@ def cpu_baseline(n, seed=3):
                       f"{cores} workers) of a {n}^3 six-component state: {dt:.2f} s"}
 
 
+def bench_c4(args):
+    """Batched sweep (C4): 64 instances on uneven grids {128, 192, 256}^3,
+    each init + its own steps to the focus + 64^3 cut-out, all in one
+    captured graph per sweep.  One bench step = one sweep."""
+    import torch
+    from paper_2010_00409_amd import tfocus as tf
+    from synthetic import configs
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    insts = configs.c4()
+    grids = [tf.tf_layer_grid(c["pulse"], c["n"], c["spacing"]) for c in insts]
+    pulses = [c["pulse"] for c in insts]
+    nsteps = [c["steps"] for c in insts]
+    dts = [c["dt"] for c in insts]
+    win = insts[0]["window"]
+    dst = torch.empty((len(insts), 6, win["wz"], win["wy"], win["wx"]), dtype=torch.float32, device="cuda")
+    updates = sum(c["n"][0] ** 3 * c["steps"] for c in insts)
+    with tf.Batch(grids, pulses, "f32", stream) as b:
+        for _ in range(args.warmup):
+            b.run(nsteps, dts, win, dst)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.run(nsteps, dts, win, dst)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    el = t1 - t0
+    sizes = {}
+    for c in insts:
+        sizes[c["n"][0]] = sizes.get(c["n"][0], 0) + 1
+    print(json.dumps({
+        "metric": "batched sweep cell-updates/s (64 uneven grids, one graph per sweep)",
+        "value": updates * args.steps / el, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "C4: 64 instances, sizes " + json.dumps(sizes) +
+                   ", dx = lambda/12, f ~ U[0.4, 2], CEP, GDD; steps to the focus; 64^3 cut-out",
+                   "cell_updates_per_sweep": updates, "total_steps": sum(nsteps)},
+        "focal_peak_abs": float(dst.abs().max().item()),
+    }), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "c4":
+        bench_c4(args)
+        return
     import torch
     from paper_2010_00409_amd import tfocus as tf
     from synthetic import configs

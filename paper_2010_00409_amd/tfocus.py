@@ -11,6 +11,8 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libtfocus.so")
+# kernel plans tuned on MI355X (tf_tune); used unless TFOCUS_PLAN_FILE is set
+DEFAULT_PLANS = os.path.join(HERE, "plans", "gfx950.txt")
 
 TF_OK, TF_EINVAL, TF_EUNSUPPORTED, TF_ENOMEM, TF_EDEVICE, TF_ESTATE, TF_EDOMAIN, TF_ENONFINITE = \
     0, -1, -2, -3, -4, -5, -6, -7
@@ -109,6 +111,8 @@ def load():
             fn.argtypes = args
             fn.restype = res
         _lib = lib
+        if not os.environ.get("TFOCUS_PLAN_FILE") and os.path.exists(DEFAULT_PLANS):
+            lib.tf_set_plan_file(DEFAULT_PLANS.encode())
     return _lib
 
 

@@ -191,3 +191,18 @@ def test_determinism_bitwise():
     a, _ = run_gpu(g, "f32", st.astype(np.float32), 3, 0.4)
     b, _ = run_gpu(g, "f32", st.astype(np.float32), 3, 0.4)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("n", [64, 128, 192])
+@pytest.mark.parametrize("zvariant", [0, 1, 2, 3])
+@pytest.mark.parametrize("row_block", ["8", "n"])
+def test_every_kernel_plan_keeps_parity(n, zvariant, row_block, monkeypatch):
+    """Each z strip shape and y row blocking the tuner can pick."""
+    monkeypatch.setenv("TFOCUS_ZVARIANT", str(zvariant))
+    monkeypatch.setenv("TFOCUS_ROW_BLOCK", str(n) if row_block == "n" else row_block)
+    d = 0.3
+    g, st = transverse_state(n + zvariant, (n, n, n), d)
+    st = st.astype(np.float32).astype(np.float64)
+    out, _ = run_gpu(g, "f32", st, 2, 0.41)
+    Eo, Bo = psatd.step_fft(st[:3], st[3:], spacing(g), 0.41, nsteps=2)
+    assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= 2 * F32_TOL

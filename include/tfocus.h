@@ -268,6 +268,78 @@ tf_status tf_set_plan_file(const char* path);
  * ms" into plan_path.  best_ms (nullable) receives the best ms per step. */
 tf_status tf_tune(const int32_t* sizes, int32_t n, int32_t precision, const char* plan_path, double* best_ms);
 
+/* ---- learned surrogate (Fourier neural operator) ----------------------- */
+
+/* The paper motivates the method as a fast generator of many focusing runs,
+ * for instance as training data for learned models (Sec. I, Sec. III.B.3).
+ * This surrogate is trained on the solver's focal windows and maps eight
+ * pulse and optics parameters, each normalised to [0, 1], to the
+ * six-component field on a 64^3 focal window.  The plain solver stays its
+ * fallback and the judge of its error.
+ *
+ * Architecture (fixed): lift [p, x, y, z] -> 32 channels (x, y, z the node
+ * coordinates scaled to [-1, 1)); three Fourier layers
+ *   z_l = irfft3(R_l . rfft3(v_l) on the kept modes) + v_l W_l + b_l,
+ *   v_{l+1} = GELU(z_l) except after the last layer;
+ * kept modes kx in [0, 12), ky, kz in [0, 12) U [52, 64), mode
+ * q = (kz_i * 24 + ky_i) * 12 + kx (i: position in the kept list); R_l[q] a
+ * complex 32 x 32 matrix; projection GELU(v P1 + c1) P2 + c2 to 6 outputs.
+ * Loss: mean over the batch of ||out - y|| / ||y||.
+ *
+ * Parameters are one float32 vector of tf_fno_param_count() entries:
+ * W0 (11 x 32), b0 (32), then for each layer W (32 x 32), b (32),
+ * R (6912 x 32 x 32 complex stored [q][c][o][re, im]), then P1 (32 x 128),
+ * c1 (128), P2 (128 x 6), c2 (6); matrices row-major, input index first.
+ * Every contraction runs on bf16 MFMA with float32 accumulation; learned
+ * weights are used as bf16 copies of the float32 master weights.
+ *
+ * Device layouts: params [B][8]; out and target [B][6][64][64][64]
+ * (components Ex Ey Ez Bx By Bz, x fastest); node tensors v, u
+ * [B][64 z][64 y][64 x][32 c]; modes [B][24 kz][2 re/im][24 ky][12 kx][32 c]. */
+
+typedef struct tf_fno tf_fno;
+
+int64_t tf_fno_param_count(void);
+
+/* Allocate a surrogate for batches up to max_batch (1..128) on the current
+ * device.  training = 0 allocates only what inference needs (about
+ * 80 MB per sample); training = 1 also keeps activations, gradients and Adam
+ * state (about 0.45 GB per sample plus 0.8 GB).  Parameters start at 0. */
+tf_status tf_fno_create(int32_t max_batch, int32_t training, void* hip_stream, tf_fno** out);
+tf_status tf_fno_destroy(tf_fno* f);
+
+/* Copy the flat parameter vector in or out.  Setting resets Adam. */
+tf_status tf_fno_set_params(tf_fno* f, const float* src, int32_t src_on_device);
+tf_status tf_fno_get_params(tf_fno* f, float* dst, int32_t dst_on_device);
+
+/* Inference: out <- surrogate(params) for batch samples (device pointers).
+ * Asynchronous on the surrogate's stream. */
+tf_status tf_fno_forward(tf_fno* f, const float* params, int32_t batch, float* out);
+
+/* Loss and gradient of the batch (device params and target).  loss (host,
+ * nullable) receives the loss; grad (host, nullable) receives the gradient in
+ * the flat parameter layout.  Either pointer synchronises.  TF_ESTATE for an
+ * inference-only surrogate. */
+tf_status tf_fno_loss_grad(tf_fno* f, const float* params, const float* target, int32_t batch, double* loss,
+                           float* grad);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with
+ * learning rate lr on the batch loss.  loss (host, nullable) as above. */
+tf_status tf_fno_train_step(tf_fno* f, const float* params, const float* target, int32_t batch, double lr,
+                            double* loss);
+
+/* The operator's truncated transforms on their own (device pointers):
+ * modes <- rfft3(v) on the kept modes; u <- irfft3 of the kept modes with
+ * zeros elsewhere (scipy / numpy normalisation: the inverse carries 1/64^3). */
+tf_status tf_fno_spectral_forward(tf_fno* f, const float* v, int32_t batch, float* modes);
+tf_status tf_fno_spectral_inverse(tf_fno* f, const float* modes, int32_t batch, float* u);
+
+/* Checkpoint the float32 parameters (and, for a training surrogate, the Adam
+ * moments and step) to a file, and read one back.  TF_EINVAL for a file of
+ * another architecture. */
+tf_status tf_fno_save(tf_fno* f, const char* path);
+tf_status tf_fno_load(tf_fno* f, const char* path);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,1190 @@
+// Learned surrogate: a Fourier neural operator that maps eight pulse and
+// optics parameters to the six-component focal-window field, trained on the
+// solver's own output.  The paper motivates fast generation of many focusing
+// runs as training data for learned models (Sec. I and Sec. III.B.3); the
+// operator itself is this library's.
+//
+// Architecture (fixed): 64^3 window, width 32, 12 kept modes per axis
+// (kx in [0, 12), ky and kz in [0, 12) U [52, 64)), 3 Fourier layers,
+// projection 32 -> 128 -> 6, GELU(x) = x (1 + erf(x / sqrt 2)) / 2.
+//   v0      = [p, x, y, z] W0 + b0                      (lift, fp32)
+//   z_l     = irfft3(R_l . rfft3(v_l)|kept) + v_l W_l + b_l
+//   v_l+1   = GELU(z_l) (l < 2),  v_3 = z_2
+//   out     = GELU(v_3 P1 + c1) P2 + c2
+// Loss: mean over samples of ||out - y|| / ||y||.
+//
+// Arithmetic: every contraction runs on bf16 MFMA with fp32 accumulation.
+// Learned weights enter as bf16 working copies of fp32 master weights; the
+// truncated DFT matrices (float64-built) and the activations they multiply
+// are split into bf16 hi + lo parts and multiplied with three MFMAs, which
+// keeps the spectral transforms at about fp32 accuracy.
+//
+// Data layout (fp32, one sample; B samples are stacked outermost):
+//   node tensor  [z][y][x][c]                 64^3 x 32, channel fastest
+//   X1 (x pass)  [z][y][s][kx][c]             s: 0 real, 1 imaginary
+//   X2 (y pass)  [ky][z][s][kx][c]
+//   modes        [kz][s][ky][kx][c]           mode q = (kz * 24 + ky) * 12 + kx
+//   out, target  [6][z][y][x]
+// Every stage is "a small constant matrix applied along one axis" and runs as
+// one strided GEMM whose row/column index maps are two-level affine.
+#include "engine.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+
+namespace tf {
+namespace fno {
+
+constexpr int N = 64, N3 = N * N * N, C = 32, M = 12, NPAR = 8, HID = 128, NOUT = 6, LAYERS = 3;
+constexpr int KS = 2 * M;                 // kept ky / kz values
+constexpr int NMODES = KS * KS * M;       // 6912
+constexpr int LINE = M * C;               // 384 floats: one (kx, c) block
+constexpr int64_t NODE_SZ = int64_t(N3) * C;                // node tensor per sample
+constexpr int64_t X1_SZ = int64_t(N) * N * 2 * LINE;        // 3,145,728
+constexpr int64_t X2_SZ = int64_t(KS) * N * 2 * LINE;       // 1,179,648
+constexpr int64_t X3_SZ = int64_t(KS) * 2 * KS * LINE;      // 442,368
+constexpr int64_t OUT_SZ = int64_t(NOUT) * N3;
+constexpr int CHUNK = 4096;               // nodes per split-K block of the weight gradients
+constexpr int NCHUNK = N3 / CHUNK;
+
+// Flat parameter vector (fp32): W0 (11x32), b0, then per layer W (32x32),
+// b (32), R (NMODES x 32 x 32 complex as [q][c][o][re, im]), then P1 (32x128),
+// c1, P2 (128x6), c2.  Row-major, input index first.
+constexpr int64_t OFF_W0 = 0, OFF_B0 = 11 * C;
+constexpr int64_t LAYER_SZ = C * C + C + int64_t(NMODES) * C * C * 2;
+constexpr int64_t OFF_L0 = OFF_B0 + C;
+constexpr int64_t off_w(int l) { return OFF_L0 + l * LAYER_SZ; }
+constexpr int64_t off_b(int l) { return off_w(l) + C * C; }
+constexpr int64_t off_r(int l) { return off_b(l) + C; }
+constexpr int64_t OFF_P1 = OFF_L0 + LAYERS * LAYER_SZ;
+constexpr int64_t OFF_C1 = OFF_P1 + C * HID;
+constexpr int64_t OFF_P2 = OFF_C1 + HID;
+constexpr int64_t OFF_C2 = OFF_P2 + HID * NOUT;
+constexpr int64_t NPARAMS = OFF_C2 + NOUT;
+
+typedef __bf16 bf16;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+__device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_d(float x) {
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+__device__ __forceinline__ float ldf(const float* p) { return *p; }
+__device__ __forceinline__ float ldf(const bf16* p) { return (float)*p; }
+
+// ---------------------------------------------------------------------------
+// Generic strided GEMM  C[b] = alpha * A[b] (M x K) . B[b] (K x N)  (+= C[b])
+// ---------------------------------------------------------------------------
+
+// Two-level affine index map: i -> (i >> sh) * hi + (i & (2^sh - 1)) * lo.
+struct Ix {
+    int sh, hi, lo;
+};
+__host__ __device__ __forceinline__ int64_t ixoff(Ix a, int i) {
+    return int64_t(i >> a.sh) * a.hi + int64_t(i & ((1 << a.sh) - 1)) * a.lo;
+}
+
+struct Operand {
+    const void* p;        // nullptr: every element is 1
+    int64_t b1, b2;       // element strides of blockIdx.y and blockIdx.z
+    Ix r, c;              // row and column maps
+    int ones_from;        // rows >= ones_from read 1 (A only; large value: none)
+    int fast_k;           // consecutive threads walk k (k is the contiguous index)
+};
+struct Result {
+    float* p;
+    int64_t b1, b2;
+    Ix r, c;
+    float alpha;
+    int accumulate;
+};
+struct GemmArgs {
+    Operand a, b;
+    Result c;
+    int M, N, K;
+};
+
+// Each wave owns 32x32 output sub-tiles; the K loop stages 32-wide slices of
+// A and B in LDS as bf16 (hi and, for SPLIT, lo parts), k contiguous so each
+// lane reads its eight k values with one 16-byte LDS load.
+template <int BM, int BN, int NW, typename TA, typename TB, bool SPLIT>
+__global__ __launch_bounds__(64 * NW) void k_gemm(GemmArgs g) {
+    constexpr int BK = 32, PITCH = BK + 8, NT = 64 * NW;
+    constexpr int SUBN = BN / 32, SUB = (BM / 32) * SUBN, PER = SUB / NW;
+    static_assert(SUB % NW == 0, "sub-tiles must divide among the waves");
+    constexpr int NP = SPLIT ? 2 : 1;
+    __shared__ __attribute__((aligned(16))) bf16 sa[NP][BM * PITCH];
+    __shared__ __attribute__((aligned(16))) bf16 sb[NP][BN * PITCH];
+
+    const int tilesN = (g.N + BN - 1) / BN;
+    const int m0 = (blockIdx.x / tilesN) * BM, n0 = (blockIdx.x % tilesN) * BN;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t = lane & 31, grp = lane >> 5;
+    const TA* A = g.a.p ? (const TA*)g.a.p + blockIdx.y * g.a.b1 + blockIdx.z * g.a.b2 : nullptr;
+    const TB* B = g.b.p ? (const TB*)g.b.p + blockIdx.y * g.b.b1 + blockIdx.z * g.b.b2 : nullptr;
+
+    f32x16 acc[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[p][r] = 0.0f;
+
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+        for (int e = threadIdx.x; e < BM * BK; e += NT) {
+            int i, k;
+            if (g.a.fast_k) { i = e / BK; k = e % BK; }
+            else            { i = e % BM; k = e / BM; }
+            const int gi = m0 + i, gk = k0 + k;
+            float v = 0.0f;
+            if (gi < g.M && gk < g.K)
+                v = (!A || gi >= g.a.ones_from) ? 1.0f : ldf(A + ixoff(g.a.r, gi) + ixoff(g.a.c, gk));
+            const bf16 hi = (bf16)v;
+            sa[0][i * PITCH + k] = hi;
+            if constexpr (SPLIT) sa[NP - 1][i * PITCH + k] = (bf16)(v - (float)hi);
+        }
+        for (int e = threadIdx.x; e < BN * BK; e += NT) {
+            int j, k;
+            if (g.b.fast_k) { j = e / BK; k = e % BK; }
+            else            { j = e % BN; k = e / BN; }
+            const int gj = n0 + j, gk = k0 + k;
+            float v = 0.0f;
+            if (gj < g.N && gk < g.K) v = B ? ldf(B + ixoff(g.b.r, gk) + ixoff(g.b.c, gj)) : 1.0f;
+            const bf16 hi = (bf16)v;
+            sb[0][j * PITCH + k] = hi;
+            if constexpr (SPLIT) sb[NP - 1][j * PITCH + k] = (bf16)(v - (float)hi);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int st = wave * PER + p, mt = st / SUBN, nt = st % SUBN;
+#pragma unroll
+            for (int ks = 0; ks < BK / 16; ++ks) {
+                const int ao = (mt * 32 + t) * PITCH + ks * 16 + 8 * grp;
+                const int bo = (nt * 32 + t) * PITCH + ks * 16 + 8 * grp;
+                const bf16x8 ah = *(const bf16x8*)&sa[0][ao];
+                const bf16x8 bh = *(const bf16x8*)&sb[0][bo];
+                acc[p] = mfma(ah, bh, acc[p]);
+                if constexpr (SPLIT) {
+                    const bf16x8 al = *(const bf16x8*)&sa[NP - 1][ao];
+                    const bf16x8 bl = *(const bf16x8*)&sb[NP - 1][bo];
+                    acc[p] = mfma(ah, bl, acc[p]);
+                    acc[p] = mfma(al, bh, acc[p]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    float* Cp = g.c.p + blockIdx.y * g.c.b1 + blockIdx.z * g.c.b2;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int st = wave * PER + p, mt = st / SUBN, nt = st % SUBN;
+        const int col = n0 + nt * 32 + t;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = m0 + mt * 32 + 8 * (r >> 2) + 4 * grp + (r & 3);
+            if (row < g.M && col < g.N) {
+                float* d = Cp + ixoff(g.c.r, row) + ixoff(g.c.c, col);
+                const float v = g.c.alpha * acc[p][r];
+                *d = g.c.accumulate ? *d + v : v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused per-line kernels
+// ---------------------------------------------------------------------------
+
+// One wave per x-line (64 nodes, two 32-node halves):
+//   acc[x][j] = sum_k CM[x][k] LN[k][j]   (k < 24, split bf16)
+//             + sum_c ACT[x][c] Wt[c][j]  (bf16)
+// Forward (inverse x transform + pointwise branch of a layer):
+//   CM = inverse x matrix, LN = the line's (s, kx) x c block, Wt = W,
+//   z = acc + b; zout <- z; out <- GELU(z) or z.
+// Backward (adjoint): CM = transpose of the forward x matrix, LN = gradient
+//   block, ACT = dL/dz_l, Wt = W^T; out <- acc * GELU'(z_{l-1}) or acc.
+struct LineArgs {
+    const float* cm;      // [64][24]
+    const float* ln;      // [lines][24][32]
+    const float* act;     // [lines][64][32], or nullptr: no pointwise term
+    const bf16* w;        // [32][32] row-major W[c][o]
+    const float* bias;    // [32] (forward) or nullptr
+    const float* zprev;   // backward: z_{l-1} for GELU', or nullptr
+    float* zout;          // forward: pre-activation, or nullptr
+    float* out;
+    int nlines;
+    int bwd;
+    int act_gelu;         // forward: out = GELU(z)
+};
+
+__global__ __launch_bounds__(256) void k_lineout(LineArgs a) {
+    const int lane = threadIdx.x & 63, t = lane & 31, grp = lane >> 5;
+    const int line = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (line >= a.nlines) return;
+
+    // constant fragments: CM rows (split) and the weight columns
+    bf16x8 cmh[2][2], cml[2][2], wf[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = 16 * s + 8 * grp + e;
+                const float v = k < 24 ? a.cm[(32 * h + t) * 24 + k] : 0.0f;
+                const bf16 hi = (bf16)v;
+                cmh[h][s][e] = hi;
+                cml[h][s][e] = (bf16)(v - (float)hi);
+            }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 16 * s + 8 * grp + e;
+            wf[s][e] = a.bwd ? a.w[t * C + k] : a.w[k * C + t];
+        }
+
+    // spectral block of this line as the B operand (k = (s, kx) < 24, column t)
+    const float* ln = a.ln + int64_t(line) * 24 * C;
+    bf16x8 lh[2], ll[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 16 * s + 8 * grp + e;
+            const float v = k < 24 ? ln[k * C + t] : 0.0f;
+            const bf16 hi = (bf16)v;
+            lh[s][e] = hi;
+            ll[s][e] = (bf16)(v - (float)hi);
+        }
+
+    const int64_t base = int64_t(line) * N * C;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        f32x16 acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            acc = mfma(cmh[h][s], lh[s], acc);
+            acc = mfma(cmh[h][s], ll[s], acc);
+            acc = mfma(cml[h][s], lh[s], acc);
+        }
+        if (a.act) {
+            const float* ap = a.act + base + (32 * h + t) * C + 8 * grp;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const float4 u0 = *(const float4*)(ap + 16 * s);
+                const float4 u1 = *(const float4*)(ap + 16 * s + 4);
+                bf16x8 af;
+                af[0] = (bf16)u0.x; af[1] = (bf16)u0.y; af[2] = (bf16)u0.z; af[3] = (bf16)u0.w;
+                af[4] = (bf16)u1.x; af[5] = (bf16)u1.y; af[6] = (bf16)u1.z; af[7] = (bf16)u1.w;
+                acc = mfma(af, wf[s], acc);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int x = 32 * h + 8 * (r >> 2) + 4 * grp + (r & 3);
+            const int64_t idx = base + x * C + t;
+            float v = acc[r];
+            if (!a.bwd) {
+                if (a.bias) v += a.bias[t];
+                if (a.zout) a.zout[idx] = v;
+                a.out[idx] = a.act_gelu ? gelu(v) : v;
+            } else {
+                if (a.zprev) v *= gelu_d(a.zprev[idx]);
+                a.out[idx] = v;
+            }
+        }
+    }
+}
+
+// Projection 32 -> 128 -> 6 per 32-node tile, one wave per tile.  The hidden
+// layer is computed transposed (h^T = P1^T v^T): its MFMA accumulator holds,
+// in lane (node t, group g), register r, the hidden unit
+//   kappa(r) = 8 (r >> 2) + 4 g + (r & 3)  within a 32-unit block,
+// which is exactly the k slot an MFMA operand in that lane needs when the
+// K index is relabelled by kappa.  So the hidden layer feeds the next
+// contraction straight from registers, with the constant operand (P2 or P1)
+// gathered in the same kappa order.
+struct ProjArgs {
+    const float* v;       // [B][N3][32]
+    const bf16* p1;       // [32][128]
+    const float* c1;      // [128]
+    const bf16* p2;       // [128][6]
+    const float* c2;      // [6]
+    float* out;           // forward: [B][6][N3]
+    const float* gout;    // backward: dL/dout [B][6][N3]
+    float* gv;            // backward: [B][N3][32]
+    bf16* hT;             // backward: GELU(hidden) [B][128][N3]
+    bf16* ghT;            // backward: dL/d(pre-activation) [B][128][N3]
+    int ntiles;
+    int bwd;
+};
+
+__device__ __forceinline__ int kappa(int s, int grp, int e) { return 16 * s + 8 * (e >> 2) + 4 * grp + (e & 3); }
+
+__global__ __launch_bounds__(256) void k_proj(ProjArgs a) {
+    const int lane = threadIdx.x & 63, t = lane & 31, grp = lane >> 5;
+    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= a.ntiles) return;
+    const int b = tile / (N3 / 32), node0 = (tile % (N3 / 32)) * 32;
+
+    // A operand of h^T = P1^T v^T: lane (hidden 32 mt + t), k = c
+    bf16x8 p1t[4][2];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) p1t[mt][s][e] = a.p1[(16 * s + 8 * grp + e) * HID + 32 * mt + t];
+
+    // B operand v^T: lane (node t), k = c
+    bf16x8 vf[2];
+    {
+        const float* vp = a.v + (int64_t(b) * N3 + node0 + t) * C + 8 * grp;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const float4 u0 = *(const float4*)(vp + 16 * s);
+            const float4 u1 = *(const float4*)(vp + 16 * s + 4);
+            vf[s][0] = (bf16)u0.x; vf[s][1] = (bf16)u0.y; vf[s][2] = (bf16)u0.z; vf[s][3] = (bf16)u0.w;
+            vf[s][4] = (bf16)u1.x; vf[s][5] = (bf16)u1.y; vf[s][6] = (bf16)u1.z; vf[s][7] = (bf16)u1.w;
+        }
+    }
+
+    if (!a.bwd) {
+        f32x16 oacc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) oacc[r] = 0.0f;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x16 acc;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+            acc = mfma(p1t[mt][0], vf[0], acc);
+            acc = mfma(p1t[mt][1], vf[1], acc);
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                bf16x8 hf, pf;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int hd = 32 * mt + kappa(s, grp, e);
+                    hf[e] = (bf16)gelu(acc[8 * s + e] + a.c1[hd]);
+                    pf[e] = t < NOUT ? a.p2[hd * NOUT + t] : (bf16)0.0f;
+                }
+                oacc = mfma(pf, hf, oacc);
+            }
+        }
+        // rows are output components: group 0 holds 0..3 (r = 0..3), group 1 holds 4, 5 (r = 0, 1)
+        float* op = a.out + int64_t(b) * OUT_SZ + node0 + t;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = 4 * grp + r;
+            if (o < NOUT) op[int64_t(o) * N3] = oacc[r] + a.c2[o];
+        }
+        return;
+    }
+
+    // backward: dL/dout^T as the B operand of dL/dh^T = P2 . dL/dout^T (K = 6 padded to 16)
+    bf16x8 gf;
+    {
+        const float* gp = a.gout + int64_t(b) * OUT_SZ + node0 + t;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int o = 8 * grp + e;
+            gf[e] = o < NOUT ? (bf16)gp[int64_t(o) * N3] : (bf16)0.0f;
+        }
+    }
+    f32x16 gvacc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) gvacc[r] = 0.0f;
+    bf16* hp = a.hT + int64_t(b) * HID * N3 + node0 + t;
+    bf16* ghp = a.ghT + int64_t(b) * HID * N3 + node0 + t;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        f32x16 acc, gacc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) { acc[r] = 0.0f; gacc[r] = 0.0f; }
+        acc = mfma(p1t[mt][0], vf[0], acc);
+        acc = mfma(p1t[mt][1], vf[1], acc);
+        bf16x8 p2f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int o = 8 * grp + e;
+            p2f[e] = o < NOUT ? a.p2[(32 * mt + t) * NOUT + o] : (bf16)0.0f;
+        }
+        gacc = mfma(p2f, gf, gacc);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            bf16x8 af, bfr;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int r = 8 * s + e;
+                const int hd = 32 * mt + kappa(s, grp, e);
+                const float pre = acc[r] + a.c1[hd];
+                const float gpre = gacc[r] * gelu_d(pre);
+                hp[int64_t(hd) * N3] = (bf16)gelu(pre);
+                const bf16 gb = (bf16)gpre;
+                ghp[int64_t(hd) * N3] = gb;
+                af[e] = gb;
+                bfr[e] = a.p1[t * HID + hd];
+            }
+            gvacc = mfma(af, bfr, gvacc);
+        }
+    }
+    float* gvp = a.gv + (int64_t(b) * N3 + node0) * C + t;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) gvp[(8 * (r >> 2) + 4 * grp + (r & 3)) * C] = gvacc[r];
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise and reduction kernels
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float coord(int i) { return float(i - N / 2) / float(N / 2); }
+
+// v0[b][node][c] = b0[c] + sum_i p[b][i] W0[i][c] + x W0[8][c] + y W0[9][c] + z W0[10][c]
+__global__ void k_lift(const float* p, const float* w0, const float* b0, float* v, int64_t total) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int c = idx & (C - 1);
+    const int64_t nb = idx >> 5;
+    const int node = int(nb % N3), b = int(nb / N3);
+    float s = b0[c];
+    for (int i = 0; i < NPAR; ++i) s += p[b * NPAR + i] * w0[i * C + c];
+    s += coord(node % N) * w0[8 * C + c];
+    s += coord((node / N) % N) * w0[9 * C + c];
+    s += coord(node / (N * N)) * w0[10 * C + c];
+    v[idx] = s;
+}
+
+// per (sample, z plane): sum_node g, and sum_node coord_d g, for every channel
+__global__ __launch_bounds__(256) void k_lift_grad_part(const float* gv, float* part) {
+    const int z = blockIdx.x, b = blockIdx.y;
+    const int c = threadIdx.x & 31, ng = threadIdx.x >> 5;
+    const float* g = gv + (int64_t(b) * N3 + int64_t(z) * N * N) * C;
+    float s = 0, sx = 0, sy = 0;
+    for (int nd = ng; nd < N * N; nd += 8) {
+        const float v = g[nd * C + c];
+        s += v;
+        sx += coord(nd % N) * v;
+        sy += coord(nd / N) * v;
+    }
+    __shared__ float red[3][8][32];
+    red[0][ng][c] = s; red[1][ng][c] = sx; red[2][ng][c] = sy;
+    __syncthreads();
+    if (ng == 0) {
+        float a0 = 0, a1 = 0, a2 = 0;
+        for (int k = 0; k < 8; ++k) { a0 += red[0][k][c]; a1 += red[1][k][c]; a2 += red[2][k][c]; }
+        float* o = part + (int64_t(b) * N + z) * 4 * C;
+        o[c] = a0; o[C + c] = a1; o[2 * C + c] = a2; o[3 * C + c] = coord(z) * a0;
+    }
+}
+
+// dL/dW0, dL/db0 from the per-plane sums (one thread per channel)
+__global__ void k_lift_grad_final(const float* part, const float* p, int B, float* grad) {
+    const int c = threadIdx.x;
+    if (c >= C) return;
+    float gw[11] = {0};
+    float gb = 0;
+    for (int b = 0; b < B; ++b) {
+        float s = 0, sx = 0, sy = 0, sz = 0;
+        for (int z = 0; z < N; ++z) {
+            const float* o = part + (int64_t(b) * N + z) * 4 * C;
+            s += o[c]; sx += o[C + c]; sy += o[2 * C + c]; sz += o[3 * C + c];
+        }
+        for (int i = 0; i < NPAR; ++i) gw[i] += p[b * NPAR + i] * s;
+        gw[8] += sx; gw[9] += sy; gw[10] += sz;
+        gb += s;
+    }
+    for (int i = 0; i < 11; ++i) grad[OFF_W0 + i * C + c] = gw[i];
+    grad[OFF_B0 + c] = gb;
+}
+
+// per (chunk, sample): sum (out - y)^2 and sum y^2 in float64
+__global__ __launch_bounds__(256) void k_loss_part(const float* out, const float* y, double* part) {
+    const int ch = blockIdx.x, b = blockIdx.y;
+    const int64_t len = OUT_SZ / gridDim.x;
+    const float* o = out + int64_t(b) * OUT_SZ + ch * len;
+    const float* t = y + int64_t(b) * OUT_SZ + ch * len;
+    double sd = 0, sy = 0;
+    for (int64_t i = threadIdx.x; i < len; i += 256) {
+        const double d = double(o[i]) - double(t[i]);
+        sd += d * d;
+        sy += double(t[i]) * double(t[i]);
+    }
+    __shared__ double rd[256], ry[256];
+    rd[threadIdx.x] = sd; ry[threadIdx.x] = sy;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) { rd[threadIdx.x] += rd[threadIdx.x + w]; ry[threadIdx.x] += ry[threadIdx.x + w]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[(int64_t(b) * gridDim.x + ch) * 2] = rd[0];
+        part[(int64_t(b) * gridDim.x + ch) * 2 + 1] = ry[0];
+    }
+}
+
+// res[0] = loss; res[1 + b] = dL/dout scale 1 / (B ||d_b|| ||y_b||)
+__global__ void k_loss_final(const double* part, int nch, int B, double* res) {
+    if (threadIdx.x != 0) return;
+    double L = 0;
+    for (int b = 0; b < B; ++b) {
+        double sd = 0, sy = 0;
+        for (int k = 0; k < nch; ++k) { sd += part[(b * nch + k) * 2]; sy += part[(b * nch + k) * 2 + 1]; }
+        const double nd = sqrt(sd), ny = sqrt(sy);
+        L += nd / ny;
+        res[1 + b] = nd > 0 ? 1.0 / (double(B) * nd * ny) : 0.0;
+    }
+    res[0] = L / B;
+}
+
+__global__ void k_gout(const float* out, const float* y, const double* res, float* g, int64_t total) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int b = int(i / OUT_SZ);
+    g[i] = float(double(out[i] - y[i]) * res[1 + b]);
+}
+
+// dst[e] = sum_p part[p * len + e], in a fixed order
+__global__ void k_reduce(const float* part, int nparts, int len, float* dst) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= len) return;
+    float s = 0;
+    for (int p = 0; p < nparts; ++p) s += part[int64_t(p) * len + e];
+    dst[e] = s;
+}
+
+// dL/dR from the real 64x64 block gradient G* of Y* = X* R*:
+//   re = G*[c][o] + G*[32+c][32+o],  im = G*[c][32+o] - G*[32+c][o]
+__global__ void k_fold_r(const float* gs, float* gr) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= int64_t(NMODES) * C * C) return;
+    const int o = i & 31, c = (i >> 5) & 31;
+    const float* G = gs + (i >> 10) * 4096;
+    gr[2 * i] = G[c * 64 + o] + G[(32 + c) * 64 + 32 + o];
+    gr[2 * i + 1] = G[c * 64 + 32 + o] - G[(32 + c) * 64 + o];
+}
+
+// bf16 working copy of R as the real block matrix R*[(s,c)][(s',o)]:
+//   s = s': re,  s = 0, s' = 1: im,  s = 1, s' = 0: -im
+__global__ void k_expand_r(const float* r, bf16* rb) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= int64_t(NMODES) * 4096) return;
+    const int j = i & 63, k = (i >> 6) & 63;
+    const int64_t q = i >> 12;
+    const int s = k >> 5, c = k & 31, s2 = j >> 5, o = j & 31;
+    const float* e = r + ((q * C + c) * C + o) * 2;
+    const float v = s == s2 ? e[0] : (s == 0 ? e[1] : -e[1]);
+    rb[i] = (bf16)v;
+}
+
+__global__ void k_to_bf16(const float* src, bf16* dst, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (bf16)src[i];
+}
+
+__global__ void k_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
+                       float eps, float bc1, float bc2) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+using host::fail;
+
+inline Ix plain(int s) { return Ix{30, 0, s}; }
+inline Ix two(int sh, int hi, int lo) { return Ix{sh, hi, lo}; }
+
+// largest element offset an operand touches (all strides non-negative)
+inline int64_t max_ix(Ix a, int n) {
+    if (n <= 0) return 0;
+    const int64_t mask = (int64_t(1) << a.sh) - 1;
+    return int64_t((n - 1) >> a.sh) * a.hi + std::min<int64_t>(n - 1, mask) * a.lo;
+}
+
+typedef void (*GemmLaunch)(const GemmArgs&, int, int, hipStream_t);
+
+template <int BM, int BN, int NW, typename TA, typename TB, bool SPLIT>
+void launch(const GemmArgs& g, int by, int bz, hipStream_t st) {
+    const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+    hipLaunchKernelGGL((k_gemm<BM, BN, NW, TA, TB, SPLIT>), dim3(tiles, by, bz), dim3(64 * NW), 0, st, g);
+}
+
+struct Gemm {
+    GemmArgs g;
+    int by, bz;
+    GemmLaunch fn;
+};
+
+// Checks an operand against the size of the buffer it addresses.
+inline bool fits(const Operand& o, int rows, int cols, int by, int bz, int64_t size) {
+    if (!o.p) return true;
+    const int r = std::min(rows, o.ones_from);
+    if (r <= 0) return true;
+    const int64_t mx = int64_t(by - 1) * o.b1 + int64_t(bz - 1) * o.b2 + max_ix(o.r, r) + max_ix(o.c, cols);
+    return mx < size;
+}
+inline bool fits(const Result& o, int rows, int cols, int by, int bz, int64_t size) {
+    const int64_t mx = int64_t(by - 1) * o.b1 + int64_t(bz - 1) * o.b2 + max_ix(o.r, rows) + max_ix(o.c, cols);
+    return mx < size;
+}
+
+inline Operand opnd(const void* p, Ix r, Ix c, int64_t b1, int64_t b2, int fast_k, int ones_from = 1 << 30) {
+    return Operand{p, b1, b2, r, c, ones_from, fast_k};
+}
+inline Result res(float* p, Ix r, Ix c, int64_t b1, int64_t b2, float alpha = 1.0f, int acc = 0) {
+    return Result{p, b1, b2, r, c, alpha, acc};
+}
+
+// DFT tables, float64-built from the exact integer phase (j k mod 64)
+struct Tables {
+    std::vector<float> fx, fxT, gx, gxT, fs, fsT, gs, gsT;
+};
+
+inline int side(int i) { return i < M ? i : N - 2 * M + i; }
+
+inline Tables build_tables() {
+    Tables t;
+    auto ang = [](int a, int b) { return 2.0 * M_PI * double((int64_t(a) * b) % N) / N; };
+    t.fx.assign(24 * N, 0.f);
+    t.gx.assign(N * 24, 0.f);
+    for (int kx = 0; kx < M; ++kx)
+        for (int x = 0; x < N; ++x) {
+            const double th = ang(kx, x), mult = kx == 0 ? 1.0 : 2.0;
+            t.fx[(0 * M + kx) * N + x] = float(std::cos(th));
+            t.fx[(1 * M + kx) * N + x] = float(-std::sin(th));
+            t.gx[x * 24 + 0 * M + kx] = float(mult / N * std::cos(th));
+            t.gx[x * 24 + 1 * M + kx] = float(-mult / N * std::sin(th));
+        }
+    t.fs.assign(48 * 128, 0.f);
+    t.gs.assign(128 * 48, 0.f);
+    for (int ki = 0; ki < KS; ++ki)
+        for (int n = 0; n < N; ++n) {
+            const double th = ang(side(ki), n);
+            const double fr = std::cos(th), fi = -std::sin(th);       // e^{-i th}
+            const double gr = std::cos(th) / N, gi = std::sin(th) / N; // e^{+i th} / N
+            // forward block [[fr, -fi], [fi, fr]] at (row (ki, s'), col (n, s))
+            t.fs[(2 * ki + 0) * 128 + 2 * n + 0] = float(fr);
+            t.fs[(2 * ki + 0) * 128 + 2 * n + 1] = float(-fi);
+            t.fs[(2 * ki + 1) * 128 + 2 * n + 0] = float(fi);
+            t.fs[(2 * ki + 1) * 128 + 2 * n + 1] = float(fr);
+            // inverse block at (row (n, s), col (ki, s'))
+            t.gs[(2 * n + 0) * 48 + 2 * ki + 0] = float(gr);
+            t.gs[(2 * n + 0) * 48 + 2 * ki + 1] = float(-gi);
+            t.gs[(2 * n + 1) * 48 + 2 * ki + 0] = float(gi);
+            t.gs[(2 * n + 1) * 48 + 2 * ki + 1] = float(gr);
+        }
+    auto tr = [](const std::vector<float>& a, int r, int c) {
+        std::vector<float> o(a.size());
+        for (int i = 0; i < r; ++i)
+            for (int j = 0; j < c; ++j) o[j * r + i] = a[i * c + j];
+        return o;
+    };
+    t.fxT = tr(t.fx, 24, N);
+    t.gxT = tr(t.gx, N, 24);
+    t.fsT = tr(t.fs, 48, 128);
+    t.gsT = tr(t.gs, 128, 48);
+    return t;
+}
+
+}  // namespace fno
+}  // namespace tf
+
+using namespace tf::fno;
+using tf::host::fail;
+
+struct tf_fno {
+    int dev = 0;
+    hipStream_t st = nullptr;
+    int maxB = 0;
+    bool training = false;
+    int64_t adam_t = 0;
+    bool working_stale = true;
+
+    std::vector<void*> allocs;
+    float *prm = nullptr, *grad = nullptr, *am = nullptr, *av = nullptr;
+    bf16 *wb[LAYERS] = {}, *rb[LAYERS] = {}, *p1b = nullptr, *p2b = nullptr, *zero_w = nullptr;
+    float *fx, *fxT, *gx, *gxT, *fs, *fsT, *gs, *gsT;
+    float* V[4] = {};
+    float* Z[2] = {};
+    float* X3[LAYERS] = {};
+    float *T1 = nullptr, *T2 = nullptr, *Y = nullptr, *Y2 = nullptr;
+    float *G[2] = {};
+    float *out = nullptr, *gout = nullptr, *part = nullptr, *gstar = nullptr;
+    bf16 *hT = nullptr, *ghT = nullptr;
+    double* dres = nullptr;
+    double* lpart = nullptr;
+
+    ~tf_fno() {
+        if (st) hipStreamSynchronize(st);
+        else hipDeviceSynchronize();
+        for (void* p : allocs) hipFree(p);
+    }
+
+    template <typename T>
+    tf_status alloc(T** p, int64_t n) {
+        void* q = nullptr;
+        const hipError_t e = hipMalloc(&q, size_t(n) * sizeof(T));
+        if (e != hipSuccess) return fail(TF_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        allocs.push_back(q);
+        *p = (T*)q;
+        return TF_OK;
+    }
+};
+
+namespace {
+
+constexpr int LOSS_CH = 64;
+
+#define TRY(x)                           \
+    do {                                 \
+        tf_status s_ = (x);              \
+        if (s_ != TF_OK) return s_;      \
+    } while (0)
+
+tf_status launched() {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(TF_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return TF_OK;
+}
+
+tf_status run(tf_fno* f, const Gemm& g, int64_t sa, int64_t sb, int64_t sc) {
+    if (!fits(g.g.a, g.g.M, g.g.K, g.by, g.bz, sa) || !fits(g.g.b, g.g.K, g.g.N, g.by, g.bz, sb) ||
+        !fits(g.g.c, g.g.M, g.g.N, g.by, g.bz, sc))
+        return fail(TF_EINVAL, "internal: GEMM operand exceeds its buffer");
+    g.fn(g.g, g.by, g.bz, f->st);
+    return launched();
+}
+
+// ---- the spectral stages (per sample b = blockIdx.z) ----
+
+// x contraction: out[(s,kx)][(zy,c)] = sum_x A[(s,kx)][x] in[(zy,x,c)]
+Gemm g_xcontract(const float* A, const float* in, float* out, int B) {
+    GemmArgs g{opnd(A, plain(N), plain(1), 0, 0, 1),
+               opnd(in, plain(C), two(5, N * C, 1), 0, NODE_SZ, 0),
+               res(out, plain(C), two(5, 2 * LINE, 1), 0, X1_SZ), 24, N * N * C, N};
+    return Gemm{g, 1, B, launch<32, 128, 4, float, float, true>};
+}
+// y contraction (per z): X1 layout in, X2 layout out; A is 48 x 128
+Gemm g_ycontract(const float* A, const float* in, float* out, int B) {
+    GemmArgs g{opnd(A, plain(128), plain(1), 0, 0, 1),
+               opnd(in, plain(LINE), plain(1), int64_t(N) * 2 * LINE, X1_SZ, 0),
+               res(out, two(1, N * 2 * LINE, LINE), plain(1), 2 * LINE, X2_SZ), 48, LINE, 128};
+    return Gemm{g, N, B, launch<64, 128, 4, float, float, true>};
+}
+// z contraction (per ky): X2 layout in, mode layout out
+Gemm g_zcontract(const float* A, const float* in, float* out, int B) {
+    GemmArgs g{opnd(A, plain(128), plain(1), 0, 0, 1),
+               opnd(in, plain(LINE), plain(1), int64_t(N) * 2 * LINE, X2_SZ, 0),
+               res(out, plain(KS * LINE), plain(1), LINE, X3_SZ), 48, LINE, 128};
+    return Gemm{g, KS, B, launch<64, 128, 4, float, float, true>};
+}
+// z expansion (per ky): mode layout in, X2 layout out; A is 128 x 48
+Gemm g_zexpand(const float* A, const float* in, float* out, int B) {
+    GemmArgs g{opnd(A, plain(48), plain(1), 0, 0, 1),
+               opnd(in, plain(KS * LINE), plain(1), LINE, X3_SZ, 0),
+               res(out, plain(LINE), plain(1), int64_t(N) * 2 * LINE, X2_SZ), 128, LINE, 48};
+    return Gemm{g, KS, B, launch<64, 128, 4, float, float, true>};
+}
+// y expansion (per z): X2 layout in, X1 layout out
+Gemm g_yexpand(const float* A, const float* in, float* out, int B) {
+    GemmArgs g{opnd(A, plain(48), plain(1), 0, 0, 1),
+               opnd(in, two(1, N * 2 * LINE, LINE), plain(1), 2 * LINE, X2_SZ, 0),
+               res(out, plain(LINE), plain(1), int64_t(N) * 2 * LINE, X1_SZ), 128, LINE, 48};
+    return Gemm{g, N, B, launch<64, 128, 4, float, float, true>};
+}
+
+// ---- per-mode complex channel mixing as real 64 x 64 blocks ----
+// mode q = kz * 288 + (ky * 12 + kx): blockIdx.y = ky * 12 + kx, blockIdx.z = kz
+constexpr int64_t MODE_Y = C, MODE_Z = 2 * KS * LINE;
+
+// Y*[b][(s',o)] = sum X*[b][(s,c)] Wq[(s,c)][(s',o)]  (trans: Wq^T)
+Gemm g_mix(const float* X, const bf16* R, float* Yo, int B, bool trans) {
+    const Ix rr = trans ? plain(1) : plain(64), rc = trans ? plain(64) : plain(1);
+    GemmArgs g{opnd(X, plain(X3_SZ), two(5, KS * LINE, 1), MODE_Y, MODE_Z, 1),
+               opnd(R, rr, rc, 4096, int64_t(KS * M) * 4096, trans ? 1 : 0),
+               res(Yo, plain(X3_SZ), two(5, KS * LINE, 1), MODE_Y, MODE_Z), B, 64, 64};
+    return Gemm{g, KS * M, KS, launch<32, 64, 2, float, bf16, false>};
+}
+// G*[q][(s,c)][(s',o)] = sum_b X*[b][(s,c)] gY*[b][(s',o)]
+Gemm g_mix_grad(const float* X, const float* gY, float* gs, int B) {
+    GemmArgs g{opnd(X, two(5, KS * LINE, 1), plain(X3_SZ), MODE_Y, MODE_Z, 0),
+               opnd(gY, plain(X3_SZ), two(5, KS * LINE, 1), MODE_Y, MODE_Z, 0),
+               res(gs, plain(64), plain(1), 4096, int64_t(KS * M) * 4096), 64, 64, B};
+    return Gemm{g, KS * M, KS, launch<64, 64, 4, float, float, false>};
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t tf_fno_param_count(void) { return NPARAMS; }
+
+tf_status tf_fno_create(int32_t max_batch, int32_t training, void* hip_stream, tf_fno** out) {
+    if (!out) return fail(TF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_batch < 1 || max_batch > 128) return fail(TF_EINVAL, "max_batch must be in [1, 128]");
+    std::unique_ptr<tf_fno> f(new tf_fno());
+    f->maxB = max_batch;
+    f->training = training != 0;
+    f->st = (hipStream_t)hip_stream;
+    TF_HIP(hipGetDevice(&f->dev));
+    const int64_t B = max_batch;
+
+    TRY(f->alloc(&f->prm, NPARAMS));
+    TF_HIP(hipMemset(f->prm, 0, NPARAMS * sizeof(float)));
+    for (int l = 0; l < LAYERS; ++l) {
+        TRY(f->alloc(&f->wb[l], C * C));
+        TRY(f->alloc(&f->rb[l], int64_t(NMODES) * 4096));
+    }
+    TRY(f->alloc(&f->p1b, C * HID));
+    TRY(f->alloc(&f->p2b, HID * NOUT));
+
+    Tables t = build_tables();
+    float* tab = nullptr;
+    const int64_t ntab = 4 * 24 * N + 4 * 48 * 128;
+    TRY(f->alloc(&tab, ntab));
+    std::vector<float> all;
+    auto put = [&](const std::vector<float>& v, float** p) {
+        *p = tab + all.size();
+        all.insert(all.end(), v.begin(), v.end());
+    };
+    put(t.fx, &f->fx); put(t.fxT, &f->fxT); put(t.gx, &f->gx); put(t.gxT, &f->gxT);
+    put(t.fs, &f->fs); put(t.fsT, &f->fsT); put(t.gs, &f->gs); put(t.gsT, &f->gsT);
+    TF_HIP(hipMemcpy(tab, all.data(), all.size() * sizeof(float), hipMemcpyHostToDevice));
+
+    TRY(f->alloc(&f->V[0], B * NODE_SZ));
+    TRY(f->alloc(&f->V[1], B * NODE_SZ));
+    TRY(f->alloc(&f->T1, B * X1_SZ));
+    TRY(f->alloc(&f->T2, B * X2_SZ));
+    TRY(f->alloc(&f->X3[0], B * X3_SZ));
+    TRY(f->alloc(&f->Y, B * X3_SZ));
+    TRY(f->alloc(&f->out, B * OUT_SZ));
+    TRY(f->alloc(&f->dres, 1 + B));
+    TRY(f->alloc(&f->lpart, B * LOSS_CH * 2));
+    if (f->training) {
+        TRY(f->alloc(&f->grad, NPARAMS));
+        TRY(f->alloc(&f->am, NPARAMS));
+        TRY(f->alloc(&f->av, NPARAMS));
+        TF_HIP(hipMemset(f->am, 0, NPARAMS * sizeof(float)));
+        TF_HIP(hipMemset(f->av, 0, NPARAMS * sizeof(float)));
+        TRY(f->alloc(&f->V[2], B * NODE_SZ));
+        TRY(f->alloc(&f->V[3], B * NODE_SZ));
+        TRY(f->alloc(&f->Z[0], B * NODE_SZ));
+        TRY(f->alloc(&f->Z[1], B * NODE_SZ));
+        TRY(f->alloc(&f->G[0], B * NODE_SZ));
+        TRY(f->alloc(&f->G[1], B * NODE_SZ));
+        TRY(f->alloc(&f->X3[1], B * X3_SZ));
+        TRY(f->alloc(&f->X3[2], B * X3_SZ));
+        TRY(f->alloc(&f->Y2, B * X3_SZ));
+        TRY(f->alloc(&f->gout, B * OUT_SZ));
+        TRY(f->alloc(&f->hT, B * HID * N3));
+        TRY(f->alloc(&f->ghT, B * HID * N3));
+        TRY(f->alloc(&f->part, B * NCHUNK * 33 * HID));
+        TRY(f->alloc(&f->gstar, int64_t(NMODES) * 4096));
+    }
+    TF_HIP(hipDeviceSynchronize());
+    *out = f.release();
+    return TF_OK;
+}
+
+tf_status tf_fno_destroy(tf_fno* f) {
+    delete f;
+    return TF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+tf_status refresh_working(tf_fno* f) {
+    if (!f->working_stale) return TF_OK;
+    for (int l = 0; l < LAYERS; ++l) {
+        hipLaunchKernelGGL(k_to_bf16, dim3((C * C + 255) / 256), dim3(256), 0, f->st, f->prm + off_w(l), f->wb[l],
+                           C * C);
+        const int64_t n = int64_t(NMODES) * 4096;
+        hipLaunchKernelGGL(k_expand_r, dim3((n + 255) / 256), dim3(256), 0, f->st, f->prm + off_r(l), f->rb[l]);
+    }
+    hipLaunchKernelGGL(k_to_bf16, dim3((C * HID + 255) / 256), dim3(256), 0, f->st, f->prm + OFF_P1, f->p1b, C * HID);
+    hipLaunchKernelGGL(k_to_bf16, dim3((HID * NOUT + 255) / 256), dim3(256), 0, f->st, f->prm + OFF_P2, f->p2b,
+                       HID * NOUT);
+    TRY(launched());
+    f->working_stale = false;
+    return TF_OK;
+}
+
+// Forward pass.  Training keeps v_l, z_l and the modes of every layer for the
+// backward pass; inference ping-pongs two node tensors.
+tf_status forward(tf_fno* f, const float* params, int B, float* out) {
+    TRY(refresh_working(f));
+    const int64_t nb = B;
+    {
+        const int64_t tot = nb * NODE_SZ;
+        hipLaunchKernelGGL(k_lift, dim3((tot + 255) / 256), dim3(256), 0, f->st, params, f->prm + OFF_W0,
+                           f->prm + OFF_B0, f->V[0], tot);
+        TRY(launched());
+    }
+    const int64_t szN = nb * NODE_SZ, sz1 = nb * X1_SZ, sz2 = nb * X2_SZ, sz3 = nb * X3_SZ;
+    float* v = f->V[0];
+    for (int l = 0; l < LAYERS; ++l) {
+        float* modes = f->training ? f->X3[l] : f->X3[0];
+        TRY(run(f, g_xcontract(f->fx, v, f->T1, B), 24 * N, szN, sz1));
+        TRY(run(f, g_ycontract(f->fs, f->T1, f->T2, B), 48 * 128, sz1, sz2));
+        TRY(run(f, g_zcontract(f->fs, f->T2, modes, B), 48 * 128, sz2, sz3));
+        TRY(run(f, g_mix(modes, f->rb[l], f->Y, B, false), sz3, int64_t(NMODES) * 4096, sz3));
+        TRY(run(f, g_zexpand(f->gs, f->Y, f->T2, B), 128 * 48, sz3, sz2));
+        TRY(run(f, g_yexpand(f->gs, f->T2, f->T1, B), 128 * 48, sz2, sz1));
+        float* nv = f->training ? f->V[l + 1] : (v == f->V[0] ? f->V[1] : f->V[0]);
+        LineArgs a{f->gx, f->T1, v, f->wb[l], f->prm + off_b(l), nullptr,
+                   (f->training && l < LAYERS - 1) ? f->Z[l] : nullptr, nv, B * N * N, 0, l < LAYERS - 1};
+        hipLaunchKernelGGL(k_lineout, dim3((B * N * N + 3) / 4), dim3(256), 0, f->st, a);
+        TRY(launched());
+        v = nv;
+    }
+    ProjArgs p{v, f->p1b, f->prm + OFF_C1, f->p2b, f->prm + OFF_C2, out, nullptr, nullptr, nullptr, nullptr,
+               B * (N3 / 32), 0};
+    hipLaunchKernelGGL(k_proj, dim3((p.ntiles + 3) / 4), dim3(256), 0, f->st, p);
+    return launched();
+}
+
+// split-K weight gradient [A | 1]^T-style reductions into the flat gradient
+tf_status reduce_into(tf_fno* f, int nparts, int len, float* dst) {
+    hipLaunchKernelGGL(k_reduce, dim3((len + 255) / 256), dim3(256), 0, f->st, f->part, nparts, len, dst);
+    return launched();
+}
+
+tf_status backward(tf_fno* f, const float* params, const float* target, int B) {
+    const int64_t nb = B;
+    const int64_t szN = nb * NODE_SZ, sz1 = nb * X1_SZ, sz2 = nb * X2_SZ, sz3 = nb * X3_SZ;
+    const int64_t szO = nb * OUT_SZ, szH = nb * HID * N3, szP = nb * NCHUNK * 33 * HID;
+    // loss and dL/dout
+    hipLaunchKernelGGL(k_loss_part, dim3(LOSS_CH, B), dim3(256), 0, f->st, f->out, target, f->lpart);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, f->st, f->lpart, LOSS_CH, B, f->dres);
+    hipLaunchKernelGGL(k_gout, dim3((szO + 255) / 256), dim3(256), 0, f->st, f->out, target, f->dres, f->gout, szO);
+    TRY(launched());
+    // projection
+    float* g = f->G[0];
+    ProjArgs p{f->V[3], f->p1b, f->prm + OFF_C1, f->p2b, f->prm + OFF_C2, nullptr, f->gout, g, f->hT, f->ghT,
+               B * (N3 / 32), 1};
+    hipLaunchKernelGGL(k_proj, dim3((p.ntiles + 3) / 4), dim3(256), 0, f->st, p);
+    TRY(launched());
+    {   // [P1; c1] = [v3 | 1]^T dL/dpre
+        GemmArgs a{opnd(f->V[3], plain(1), plain(C), int64_t(CHUNK) * C, NODE_SZ, 0, C),
+                   opnd(f->ghT, plain(1), plain(N3), CHUNK, int64_t(HID) * N3, 1),
+                   res(f->part, plain(HID), plain(1), 33 * HID, int64_t(NCHUNK) * 33 * HID), 33, HID, CHUNK};
+        TRY(run(f, Gemm{a, NCHUNK, B, launch<64, 128, 4, float, bf16, false>}, szN, szH, szP));
+        TRY(reduce_into(f, B * NCHUNK, 33 * HID, f->grad + OFF_P1));
+    }
+    {   // [P2; c2] = [h | 1]^T dL/dout
+        GemmArgs a{opnd(f->hT, plain(N3), plain(1), CHUNK, int64_t(HID) * N3, 1, HID),
+                   opnd(f->gout, plain(1), plain(N3), CHUNK, OUT_SZ, 1),
+                   res(f->part, plain(NOUT), plain(1), 129 * NOUT, int64_t(NCHUNK) * 129 * NOUT), 129, NOUT, CHUNK};
+        TRY(run(f, Gemm{a, NCHUNK, B, launch<32, 32, 1, bf16, float, false>}, szH, szO, szP));
+        TRY(reduce_into(f, B * NCHUNK, 129 * NOUT, f->grad + OFF_P2));
+    }
+    for (int l = LAYERS - 1; l >= 0; --l) {
+        float* gn = g == f->G[0] ? f->G[1] : f->G[0];
+        {   // [W_l; b_l] = [v_l | 1]^T dL/dz_l
+            GemmArgs a{opnd(f->V[l], plain(1), plain(C), int64_t(CHUNK) * C, NODE_SZ, 0, C),
+                       opnd(g, plain(C), plain(1), int64_t(CHUNK) * C, NODE_SZ, 0),
+                       res(f->part, plain(C), plain(1), 33 * C, int64_t(NCHUNK) * 33 * C), 33, C, CHUNK};
+            TRY(run(f, Gemm{a, NCHUNK, B, launch<64, 32, 2, float, float, false>}, szN, szN, szP));
+            TRY(reduce_into(f, B * NCHUNK, 33 * C, f->grad + off_w(l)));
+        }
+        // adjoint of the inverse transform: modes gradient
+        TRY(run(f, g_xcontract(f->gxT, g, f->T1, B), 24 * N, szN, sz1));
+        TRY(run(f, g_ycontract(f->gsT, f->T1, f->T2, B), 48 * 128, sz1, sz2));
+        TRY(run(f, g_zcontract(f->gsT, f->T2, f->Y, B), 48 * 128, sz2, sz3));
+        // mixing: dR and dX
+        TRY(run(f, g_mix_grad(f->X3[l], f->Y, f->gstar, B), sz3, sz3, int64_t(NMODES) * 4096));
+        {
+            const int64_t n = int64_t(NMODES) * C * C;
+            hipLaunchKernelGGL(k_fold_r, dim3((n + 255) / 256), dim3(256), 0, f->st, f->gstar, f->grad + off_r(l));
+            TRY(launched());
+        }
+        TRY(run(f, g_mix(f->Y, f->rb[l], f->Y2, B, true), sz3, int64_t(NMODES) * 4096, sz3));
+        // adjoint of the forward transform, then the x line with the pointwise branch
+        TRY(run(f, g_zexpand(f->fsT, f->Y2, f->T2, B), 128 * 48, sz3, sz2));
+        TRY(run(f, g_yexpand(f->fsT, f->T2, f->T1, B), 128 * 48, sz2, sz1));
+        LineArgs a{f->fxT, f->T1, g, f->wb[l], nullptr, l > 0 ? f->Z[l - 1] : nullptr, nullptr, gn, B * N * N, 1, 0};
+        hipLaunchKernelGGL(k_lineout, dim3((B * N * N + 3) / 4), dim3(256), 0, f->st, a);
+        TRY(launched());
+        g = gn;
+    }
+    hipLaunchKernelGGL(k_lift_grad_part, dim3(N, B), dim3(256), 0, f->st, g, f->part);
+    hipLaunchKernelGGL(k_lift_grad_final, dim3(1), dim3(64), 0, f->st, f->part, params, B, f->grad);
+    return launched();
+}
+
+tf_status check_batch(tf_fno* f, int B) {
+    if (!f) return fail(TF_EINVAL, "surrogate is NULL");
+    if (B < 1 || B > f->maxB) return fail(TF_EINVAL, "batch must be in [1, max_batch]");
+    TF_HIP(hipSetDevice(f->dev));
+    return TF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tf_status tf_fno_set_params(tf_fno* f, const float* src, int32_t src_on_device) {
+    if (!f || !src) return fail(TF_EINVAL, "NULL argument");
+    TF_HIP(hipSetDevice(f->dev));
+    TF_HIP(hipMemcpyAsync(f->prm, src, NPARAMS * sizeof(float),
+                          src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, f->st));
+    if (f->training) {
+        TF_HIP(hipMemsetAsync(f->am, 0, NPARAMS * sizeof(float), f->st));
+        TF_HIP(hipMemsetAsync(f->av, 0, NPARAMS * sizeof(float), f->st));
+    }
+    f->adam_t = 0;
+    f->working_stale = true;
+    if (!src_on_device) TF_HIP(hipStreamSynchronize(f->st));
+    return TF_OK;
+}
+
+tf_status tf_fno_get_params(tf_fno* f, float* dst, int32_t dst_on_device) {
+    if (!f || !dst) return fail(TF_EINVAL, "NULL argument");
+    TF_HIP(hipSetDevice(f->dev));
+    TF_HIP(hipMemcpyAsync(dst, f->prm, NPARAMS * sizeof(float),
+                          dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, f->st));
+    if (!dst_on_device) TF_HIP(hipStreamSynchronize(f->st));
+    return TF_OK;
+}
+
+tf_status tf_fno_forward(tf_fno* f, const float* params, int32_t batch, float* out) {
+    TRY(check_batch(f, batch));
+    if (!params || !out) return fail(TF_EINVAL, "NULL argument");
+    return forward(f, params, batch, out);
+}
+
+tf_status tf_fno_loss_grad(tf_fno* f, const float* params, const float* target, int32_t batch, double* loss,
+                           float* grad) {
+    TRY(check_batch(f, batch));
+    if (!f->training) return fail(TF_ESTATE, "surrogate was created for inference only");
+    if (!params || !target) return fail(TF_EINVAL, "NULL argument");
+    TRY(forward(f, params, batch, f->out));
+    TRY(backward(f, params, target, batch));
+    if (grad) TF_HIP(hipMemcpyAsync(grad, f->grad, NPARAMS * sizeof(float), hipMemcpyDeviceToHost, f->st));
+    if (loss) TF_HIP(hipMemcpyAsync(loss, f->dres, sizeof(double), hipMemcpyDeviceToHost, f->st));
+    if (grad || loss) TF_HIP(hipStreamSynchronize(f->st));
+    return TF_OK;
+}
+
+tf_status tf_fno_train_step(tf_fno* f, const float* params, const float* target, int32_t batch, double lr,
+                            double* loss) {
+    if (!(lr >= 0.0) || !std::isfinite(lr)) return fail(TF_EINVAL, "lr must be finite and >= 0");
+    TRY(tf_fno_loss_grad(f, params, target, batch, nullptr, nullptr));
+    f->adam_t += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const float bc1 = float(1.0 - std::pow(b1, double(f->adam_t))), bc2 = float(1.0 - std::pow(b2, double(f->adam_t)));
+    hipLaunchKernelGGL(k_adam, dim3((NPARAMS + 255) / 256), dim3(256), 0, f->st, f->prm, f->am, f->av, f->grad,
+                       NPARAMS, float(lr), float(b1), float(b2), 1e-8f, bc1, bc2);
+    TRY(launched());
+    f->working_stale = true;
+    if (loss) {
+        TF_HIP(hipMemcpyAsync(loss, f->dres, sizeof(double), hipMemcpyDeviceToHost, f->st));
+        TF_HIP(hipStreamSynchronize(f->st));
+    }
+    return TF_OK;
+}
+
+tf_status tf_fno_spectral_forward(tf_fno* f, const float* v, int32_t batch, float* modes) {
+    TRY(check_batch(f, batch));
+    if (!v || !modes) return fail(TF_EINVAL, "NULL argument");
+    const int64_t nb = batch;
+    TRY(run(f, g_xcontract(f->fx, v, f->T1, batch), 24 * N, nb * NODE_SZ, nb * X1_SZ));
+    TRY(run(f, g_ycontract(f->fs, f->T1, f->T2, batch), 48 * 128, nb * X1_SZ, nb * X2_SZ));
+    return run(f, g_zcontract(f->fs, f->T2, modes, batch), 48 * 128, nb * X2_SZ, nb * X3_SZ);
+}
+
+tf_status tf_fno_spectral_inverse(tf_fno* f, const float* modes, int32_t batch, float* u) {
+    TRY(check_batch(f, batch));
+    if (!modes || !u) return fail(TF_EINVAL, "NULL argument");
+    const int64_t nb = batch;
+    TRY(run(f, g_zexpand(f->gs, modes, f->T2, batch), 128 * 48, nb * X3_SZ, nb * X2_SZ));
+    TRY(run(f, g_yexpand(f->gs, f->T2, f->T1, batch), 128 * 48, nb * X2_SZ, nb * X1_SZ));
+    LineArgs a{f->gx, f->T1, nullptr, f->wb[0], nullptr, nullptr, nullptr, u, batch * N * N, 0, 0};
+    hipLaunchKernelGGL(k_lineout, dim3((batch * N * N + 3) / 4), dim3(256), 0, f->st, a);
+    return launched();
+}
+
+// Checkpoint: magic, version, parameter count, Adam step, then the fp32
+// parameters and (when training) the two Adam moments.
+tf_status tf_fno_save(tf_fno* f, const char* path) {
+    if (!f || !path) return fail(TF_EINVAL, "NULL argument");
+    TF_HIP(hipSetDevice(f->dev));
+    std::vector<float> h(NPARAMS);
+    FILE* fp = std::fopen(path, "wb");
+    if (!fp) return fail(TF_EINVAL, std::string("cannot open ") + path);
+    const int64_t hdr[4] = {0x4f4e4646554354LL, 1, NPARAMS, f->training ? f->adam_t : -1};
+    bool ok = std::fwrite(hdr, sizeof(hdr), 1, fp) == 1;
+    const float* srcs[3] = {f->prm, f->am, f->av};
+    for (int k = 0; ok && k < (f->training ? 3 : 1); ++k) {
+        if (hipMemcpyAsync(h.data(), srcs[k], NPARAMS * sizeof(float), hipMemcpyDeviceToHost, f->st) != hipSuccess ||
+            hipStreamSynchronize(f->st) != hipSuccess) {
+            std::fclose(fp);
+            return fail(TF_EDEVICE, "copy of the parameters failed");
+        }
+        ok = std::fwrite(h.data(), sizeof(float), NPARAMS, fp) == size_t(NPARAMS);
+    }
+    ok = (std::fclose(fp) == 0) && ok;
+    return ok ? TF_OK : fail(TF_EINVAL, std::string("write failed: ") + path);
+}
+
+tf_status tf_fno_load(tf_fno* f, const char* path) {
+    if (!f || !path) return fail(TF_EINVAL, "NULL argument");
+    TF_HIP(hipSetDevice(f->dev));
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return fail(TF_EINVAL, std::string("cannot open ") + path);
+    int64_t hdr[4];
+    if (std::fread(hdr, sizeof(hdr), 1, fp) != 1 || hdr[0] != 0x4f4e4646554354LL || hdr[1] != 1 ||
+        hdr[2] != NPARAMS) {
+        std::fclose(fp);
+        return fail(TF_EINVAL, "not a surrogate checkpoint of this architecture");
+    }
+    std::vector<float> h(NPARAMS);
+    float* dsts[3] = {f->prm, f->am, f->av};
+    const int nk = (hdr[3] >= 0 && f->training) ? 3 : 1;
+    for (int k = 0; k < nk; ++k) {
+        if (std::fread(h.data(), sizeof(float), NPARAMS, fp) != size_t(NPARAMS)) {
+            std::fclose(fp);
+            return fail(TF_EINVAL, "truncated checkpoint");
+        }
+        TF_HIP(hipMemcpyAsync(dsts[k], h.data(), NPARAMS * sizeof(float), hipMemcpyHostToDevice, f->st));
+        TF_HIP(hipStreamSynchronize(f->st));
+    }
+    std::fclose(fp);
+    if (f->training) {
+        if (nk == 1) {
+            TF_HIP(hipMemsetAsync(f->am, 0, NPARAMS * sizeof(float), f->st));
+            TF_HIP(hipMemsetAsync(f->av, 0, NPARAMS * sizeof(float), f->st));
+        }
+        f->adam_t = nk == 3 ? hdr[3] : 0;
+    }
+    f->working_stale = true;
+    TF_HIP(hipStreamSynchronize(f->st));
+    return TF_OK;
+}
+
+}  // extern "C"

@@ -91,6 +91,19 @@ _SIGS = {
                  ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "tf_profile": ([_P, ctypes.c_int32], ctypes.c_int),
     "tf_profile_read": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "tf_fno_param_count": ([], ctypes.c_int64),
+    "tf_fno_create": ([ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "tf_fno_destroy": ([_P], ctypes.c_int),
+    "tf_fno_set_params": ([_P, _P, ctypes.c_int32], ctypes.c_int),
+    "tf_fno_get_params": ([_P, _P, ctypes.c_int32], ctypes.c_int),
+    "tf_fno_forward": ([_P, _P, ctypes.c_int32, _P], ctypes.c_int),
+    "tf_fno_loss_grad": ([_P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
+    "tf_fno_train_step": ([_P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)],
+                          ctypes.c_int),
+    "tf_fno_spectral_forward": ([_P, _P, ctypes.c_int32, _P], ctypes.c_int),
+    "tf_fno_spectral_inverse": ([_P, _P, ctypes.c_int32, _P], ctypes.c_int),
+    "tf_fno_save": ([_P, ctypes.c_char_p], ctypes.c_int),
+    "tf_fno_load": ([_P, ctypes.c_char_p], ctypes.c_int),
 }
 
 PASS_NAMES = ("x_forward", "y_forward", "z_step", "y_inverse", "x_inverse", "init", "readout", "other")
@@ -440,3 +453,149 @@ class Solver:
 
     def profile_read(self):
         return tf_profile_read(self.h)
+
+
+# ---- learned surrogate ----------------------------------------------------------
+
+FNO_N, FNO_WIDTH, FNO_MODES, FNO_NPARAM, FNO_HIDDEN, FNO_NOUT, FNO_LAYERS = 64, 32, 12, 8, 128, 6, 3
+FNO_NMODES = 4 * FNO_MODES ** 3
+
+
+def fno_param_shapes():
+    """(name, shape) of the flat parameter vector in order; R entries are
+    complex (stored as re, im pairs)."""
+    C, H = FNO_WIDTH, FNO_HIDDEN
+    out = [("W0", (FNO_NPARAM + 3, C)), ("b0", (C,))]
+    for l in range(1, FNO_LAYERS + 1):
+        out += [(f"W{l}", (C, C)), (f"b{l}", (C,)), (f"R{l}", (FNO_NMODES, C, C))]
+    out += [("P1", (C, H)), ("c1", (H,)), ("P2", (H, FNO_NOUT)), ("c2", (FNO_NOUT,))]
+    return out
+
+
+def fno_flatten(params):
+    """dict of numpy arrays (R complex) -> flat float32 vector."""
+    import numpy as np
+    parts = []
+    for name, shape in fno_param_shapes():
+        a = np.asarray(params[name])
+        if a.shape != shape:
+            raise ValueError(f"{name} must have shape {shape}")
+        if name.startswith("R"):
+            a = np.stack([a.real, a.imag], axis=-1)
+        parts.append(np.ascontiguousarray(a, dtype=np.float32).ravel())
+    flat = np.concatenate(parts)
+    assert flat.size == load().tf_fno_param_count()
+    return flat
+
+
+def fno_unflatten(flat):
+    """flat vector -> dict of float64 arrays (R complex128)."""
+    import numpy as np
+    flat = np.asarray(flat, dtype=np.float64)
+    out, o = {}, 0
+    for name, shape in fno_param_shapes():
+        n = int(np.prod(shape)) * (2 if name.startswith("R") else 1)
+        a = flat[o:o + n]
+        o += n
+        out[name] = (a[0::2] + 1j * a[1::2]).reshape(shape) if name.startswith("R") else a.reshape(shape)
+    return out
+
+
+class Surrogate:
+    """Owning wrapper of a tf_fno (Fourier neural operator surrogate).
+    params, targets and outputs are contiguous float32 CUDA tensors."""
+
+    def __init__(self, max_batch, training=False, stream=None):
+        h = ctypes.c_void_p()
+        _check(load().tf_fno_create(int(max_batch), 1 if training else 0, _stream_ptr(stream), ctypes.byref(h)))
+        self.h = h
+        self.max_batch = int(max_batch)
+        self.training = bool(training)
+        self.nparams = int(load().tf_fno_param_count())
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            _check(load().tf_fno_destroy(self.h))
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _dev(t, shape, what):
+        ptr, dev, nbytes, item = _buffer(t)
+        n = 1
+        for v in shape:
+            n *= v
+        if not dev or item != 4 or nbytes != 4 * n:
+            raise ValueError(f"{what} must be a float32 device tensor of shape {shape}")
+        return ptr
+
+    def set_params(self, params):
+        """dict (oracle layout) or flat float32 array/tensor."""
+        flat = fno_flatten(params) if isinstance(params, dict) else params
+        ptr, dev, nbytes, item = _buffer(flat)
+        if item != 4 or nbytes != 4 * self.nparams:
+            raise ValueError("flat parameters must be float32 of tf_fno_param_count() entries")
+        _check(load().tf_fno_set_params(self.h, ptr, dev))
+
+    def get_params(self):
+        import numpy as np
+        flat = np.empty(self.nparams, np.float32)
+        _check(load().tf_fno_get_params(self.h, flat.ctypes.data, 0))
+        return flat
+
+    def forward(self, p, out):
+        B = p.shape[0]
+        pp = self._dev(p, (B, FNO_NPARAM), "params")
+        po = self._dev(out, (B, FNO_NOUT, FNO_N, FNO_N, FNO_N), "out")
+        _check(load().tf_fno_forward(self.h, pp, B, po))
+        return out
+
+    def loss_grad(self, p, target, want_grad=True):
+        import numpy as np
+        B = p.shape[0]
+        pp = self._dev(p, (B, FNO_NPARAM), "params")
+        pt = self._dev(target, (B, FNO_NOUT, FNO_N, FNO_N, FNO_N), "target")
+        loss = ctypes.c_double()
+        g = np.empty(self.nparams, np.float32) if want_grad else None
+        _check(load().tf_fno_loss_grad(self.h, pp, pt, B, ctypes.byref(loss),
+                                        g.ctypes.data if want_grad else None))
+        return loss.value, g
+
+    def train_step(self, p, target, lr, want_loss=True):
+        B = p.shape[0]
+        pp = self._dev(p, (B, FNO_NPARAM), "params")
+        pt = self._dev(target, (B, FNO_NOUT, FNO_N, FNO_N, FNO_N), "target")
+        loss = ctypes.c_double()
+        _check(load().tf_fno_train_step(self.h, pp, pt, B, float(lr), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def spectral_forward(self, v, modes):
+        B = v.shape[0]
+        pv = self._dev(v, (B, FNO_N, FNO_N, FNO_N, FNO_WIDTH), "v")
+        pm = self._dev(modes, (B, 2 * FNO_MODES, 2, 2 * FNO_MODES, FNO_MODES, FNO_WIDTH), "modes")
+        _check(load().tf_fno_spectral_forward(self.h, pv, B, pm))
+        return modes
+
+    def spectral_inverse(self, modes, u):
+        B = u.shape[0]
+        pm = self._dev(modes, (B, 2 * FNO_MODES, 2, 2 * FNO_MODES, FNO_MODES, FNO_WIDTH), "modes")
+        pu = self._dev(u, (B, FNO_N, FNO_N, FNO_N, FNO_WIDTH), "u")
+        _check(load().tf_fno_spectral_inverse(self.h, pm, B, pu))
+        return u
+
+    def save(self, path):
+        _check(load().tf_fno_save(self.h, str(path).encode()))
+
+    def load_checkpoint(self, path):
+        _check(load().tf_fno_load(self.h, str(path).encode()))

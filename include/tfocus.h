@@ -316,6 +316,13 @@ tf_status tf_fno_get_params(tf_fno* f, float* dst, int32_t dst_on_device);
  * Asynchronous on the surrogate's stream. */
 tf_status tf_fno_forward(tf_fno* f, const float* params, int32_t batch, float* out);
 
+/* Inference as one graph replay: the whole forward pass is captured into a
+ * hipGraph on first use and replayed while params, out and batch are the
+ * same pointers and size (new parameter values are picked up; their bf16
+ * working copies are refreshed before the replay).  Results equal
+ * tf_fno_forward bit for bit.  Asynchronous on the surrogate's stream. */
+tf_status tf_fno_infer(tf_fno* f, const float* params, int32_t batch, float* out);
+
 /* Loss and gradient of the batch (device params and target).  loss (host,
  * nullable) receives the loss; grad (host, nullable) receives the gradient in
  * the flat parameter layout.  Either pointer synchronises.  TF_ESTATE for an

@@ -716,7 +716,13 @@ using tf::host::fail;
 
 struct tf_fno {
     int dev = 0;
-    hipStream_t st = nullptr;
+    hipStream_t st = nullptr;   // the caller's stream
+    hipStream_t cur = nullptr;  // stream launches go to (st, or cap while capturing)
+    hipStream_t cap = nullptr;  // private stream inference graphs are captured on
+    hipGraphExec_t exec = nullptr;
+    const float* g_params = nullptr;
+    float* g_out = nullptr;
+    int g_batch = 0;
     int maxB = 0;
     bool training = false;
     int64_t adam_t = 0;
@@ -739,6 +745,8 @@ struct tf_fno {
     ~tf_fno() {
         if (st) hipStreamSynchronize(st);
         else hipDeviceSynchronize();
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (cap) (void)hipStreamDestroy(cap);
         for (void* p : allocs) hipFree(p);
     }
 
@@ -773,7 +781,7 @@ tf_status run(tf_fno* f, const Gemm& g, int64_t sa, int64_t sb, int64_t sc) {
     if (!fits(g.g.a, g.g.M, g.g.K, g.by, g.bz, sa) || !fits(g.g.b, g.g.K, g.g.N, g.by, g.bz, sb) ||
         !fits(g.g.c, g.g.M, g.g.N, g.by, g.bz, sc))
         return fail(TF_EINVAL, "internal: GEMM operand exceeds its buffer");
-    g.fn(g.g, g.by, g.bz, f->st);
+    g.fn(g.g, g.by, g.bz, f->cur);
     return launched();
 }
 
@@ -849,7 +857,9 @@ tf_status tf_fno_create(int32_t max_batch, int32_t training, void* hip_stream, t
     f->maxB = max_batch;
     f->training = training != 0;
     f->st = (hipStream_t)hip_stream;
+    f->cur = f->st;
     TF_HIP(hipGetDevice(&f->dev));
+    TF_HIP(hipStreamCreateWithFlags(&f->cap, hipStreamNonBlocking));
     const int64_t B = max_batch;
 
     TRY(f->alloc(&f->prm, NPARAMS));
@@ -921,13 +931,13 @@ namespace {
 tf_status refresh_working(tf_fno* f) {
     if (!f->working_stale) return TF_OK;
     for (int l = 0; l < LAYERS; ++l) {
-        hipLaunchKernelGGL(k_to_bf16, dim3((C * C + 255) / 256), dim3(256), 0, f->st, f->prm + off_w(l), f->wb[l],
+        hipLaunchKernelGGL(k_to_bf16, dim3((C * C + 255) / 256), dim3(256), 0, f->cur, f->prm + off_w(l), f->wb[l],
                            C * C);
         const int64_t n = int64_t(NMODES) * 4096;
-        hipLaunchKernelGGL(k_expand_r, dim3((n + 255) / 256), dim3(256), 0, f->st, f->prm + off_r(l), f->rb[l]);
+        hipLaunchKernelGGL(k_expand_r, dim3((n + 255) / 256), dim3(256), 0, f->cur, f->prm + off_r(l), f->rb[l]);
     }
-    hipLaunchKernelGGL(k_to_bf16, dim3((C * HID + 255) / 256), dim3(256), 0, f->st, f->prm + OFF_P1, f->p1b, C * HID);
-    hipLaunchKernelGGL(k_to_bf16, dim3((HID * NOUT + 255) / 256), dim3(256), 0, f->st, f->prm + OFF_P2, f->p2b,
+    hipLaunchKernelGGL(k_to_bf16, dim3((C * HID + 255) / 256), dim3(256), 0, f->cur, f->prm + OFF_P1, f->p1b, C * HID);
+    hipLaunchKernelGGL(k_to_bf16, dim3((HID * NOUT + 255) / 256), dim3(256), 0, f->cur, f->prm + OFF_P2, f->p2b,
                        HID * NOUT);
     TRY(launched());
     f->working_stale = false;
@@ -936,12 +946,11 @@ tf_status refresh_working(tf_fno* f) {
 
 // Forward pass.  Training keeps v_l, z_l and the modes of every layer for the
 // backward pass; inference ping-pongs two node tensors.
-tf_status forward(tf_fno* f, const float* params, int B, float* out) {
-    TRY(refresh_working(f));
+tf_status forward_body(tf_fno* f, const float* params, int B, float* out) {
     const int64_t nb = B;
     {
         const int64_t tot = nb * NODE_SZ;
-        hipLaunchKernelGGL(k_lift, dim3((tot + 255) / 256), dim3(256), 0, f->st, params, f->prm + OFF_W0,
+        hipLaunchKernelGGL(k_lift, dim3((tot + 255) / 256), dim3(256), 0, f->cur, params, f->prm + OFF_W0,
                            f->prm + OFF_B0, f->V[0], tot);
         TRY(launched());
     }
@@ -958,19 +967,24 @@ tf_status forward(tf_fno* f, const float* params, int B, float* out) {
         float* nv = f->training ? f->V[l + 1] : (v == f->V[0] ? f->V[1] : f->V[0]);
         LineArgs a{f->gx, f->T1, v, f->wb[l], f->prm + off_b(l), nullptr,
                    (f->training && l < LAYERS - 1) ? f->Z[l] : nullptr, nv, B * N * N, 0, l < LAYERS - 1};
-        hipLaunchKernelGGL(k_lineout, dim3((B * N * N + 3) / 4), dim3(256), 0, f->st, a);
+        hipLaunchKernelGGL(k_lineout, dim3((B * N * N + 3) / 4), dim3(256), 0, f->cur, a);
         TRY(launched());
         v = nv;
     }
     ProjArgs p{v, f->p1b, f->prm + OFF_C1, f->p2b, f->prm + OFF_C2, out, nullptr, nullptr, nullptr, nullptr,
                B * (N3 / 32), 0};
-    hipLaunchKernelGGL(k_proj, dim3((p.ntiles + 3) / 4), dim3(256), 0, f->st, p);
+    hipLaunchKernelGGL(k_proj, dim3((p.ntiles + 3) / 4), dim3(256), 0, f->cur, p);
     return launched();
+}
+
+tf_status forward(tf_fno* f, const float* params, int B, float* out) {
+    TRY(refresh_working(f));
+    return forward_body(f, params, B, out);
 }
 
 // split-K weight gradient [A | 1]^T-style reductions into the flat gradient
 tf_status reduce_into(tf_fno* f, int nparts, int len, float* dst) {
-    hipLaunchKernelGGL(k_reduce, dim3((len + 255) / 256), dim3(256), 0, f->st, f->part, nparts, len, dst);
+    hipLaunchKernelGGL(k_reduce, dim3((len + 255) / 256), dim3(256), 0, f->cur, f->part, nparts, len, dst);
     return launched();
 }
 
@@ -979,15 +993,15 @@ tf_status backward(tf_fno* f, const float* params, const float* target, int B) {
     const int64_t szN = nb * NODE_SZ, sz1 = nb * X1_SZ, sz2 = nb * X2_SZ, sz3 = nb * X3_SZ;
     const int64_t szO = nb * OUT_SZ, szH = nb * HID * N3, szP = nb * NCHUNK * 33 * HID;
     // loss and dL/dout
-    hipLaunchKernelGGL(k_loss_part, dim3(LOSS_CH, B), dim3(256), 0, f->st, f->out, target, f->lpart);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, f->st, f->lpart, LOSS_CH, B, f->dres);
-    hipLaunchKernelGGL(k_gout, dim3((szO + 255) / 256), dim3(256), 0, f->st, f->out, target, f->dres, f->gout, szO);
+    hipLaunchKernelGGL(k_loss_part, dim3(LOSS_CH, B), dim3(256), 0, f->cur, f->out, target, f->lpart);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, f->cur, f->lpart, LOSS_CH, B, f->dres);
+    hipLaunchKernelGGL(k_gout, dim3((szO + 255) / 256), dim3(256), 0, f->cur, f->out, target, f->dres, f->gout, szO);
     TRY(launched());
     // projection
     float* g = f->G[0];
     ProjArgs p{f->V[3], f->p1b, f->prm + OFF_C1, f->p2b, f->prm + OFF_C2, nullptr, f->gout, g, f->hT, f->ghT,
                B * (N3 / 32), 1};
-    hipLaunchKernelGGL(k_proj, dim3((p.ntiles + 3) / 4), dim3(256), 0, f->st, p);
+    hipLaunchKernelGGL(k_proj, dim3((p.ntiles + 3) / 4), dim3(256), 0, f->cur, p);
     TRY(launched());
     {   // [P1; c1] = [v3 | 1]^T dL/dpre
         GemmArgs a{opnd(f->V[3], plain(1), plain(C), int64_t(CHUNK) * C, NODE_SZ, 0, C),
@@ -1020,7 +1034,7 @@ tf_status backward(tf_fno* f, const float* params, const float* target, int B) {
         TRY(run(f, g_mix_grad(f->X3[l], f->Y, f->gstar, B), sz3, sz3, int64_t(NMODES) * 4096));
         {
             const int64_t n = int64_t(NMODES) * C * C;
-            hipLaunchKernelGGL(k_fold_r, dim3((n + 255) / 256), dim3(256), 0, f->st, f->gstar, f->grad + off_r(l));
+            hipLaunchKernelGGL(k_fold_r, dim3((n + 255) / 256), dim3(256), 0, f->cur, f->gstar, f->grad + off_r(l));
             TRY(launched());
         }
         TRY(run(f, g_mix(f->Y, f->rb[l], f->Y2, B, true), sz3, int64_t(NMODES) * 4096, sz3));
@@ -1028,12 +1042,12 @@ tf_status backward(tf_fno* f, const float* params, const float* target, int B) {
         TRY(run(f, g_zexpand(f->fsT, f->Y2, f->T2, B), 128 * 48, sz3, sz2));
         TRY(run(f, g_yexpand(f->fsT, f->T2, f->T1, B), 128 * 48, sz2, sz1));
         LineArgs a{f->fxT, f->T1, g, f->wb[l], nullptr, l > 0 ? f->Z[l - 1] : nullptr, nullptr, gn, B * N * N, 1, 0};
-        hipLaunchKernelGGL(k_lineout, dim3((B * N * N + 3) / 4), dim3(256), 0, f->st, a);
+        hipLaunchKernelGGL(k_lineout, dim3((B * N * N + 3) / 4), dim3(256), 0, f->cur, a);
         TRY(launched());
         g = gn;
     }
-    hipLaunchKernelGGL(k_lift_grad_part, dim3(N, B), dim3(256), 0, f->st, g, f->part);
-    hipLaunchKernelGGL(k_lift_grad_final, dim3(1), dim3(64), 0, f->st, f->part, params, B, f->grad);
+    hipLaunchKernelGGL(k_lift_grad_part, dim3(N, B), dim3(256), 0, f->cur, g, f->part);
+    hipLaunchKernelGGL(k_lift_grad_final, dim3(1), dim3(64), 0, f->cur, f->part, params, B, f->grad);
     return launched();
 }
 
@@ -1078,6 +1092,40 @@ tf_status tf_fno_forward(tf_fno* f, const float* params, int32_t batch, float* o
     return forward(f, params, batch, out);
 }
 
+tf_status tf_fno_infer(tf_fno* f, const float* params, int32_t batch, float* out) {
+    TRY(check_batch(f, batch));
+    if (!params || !out) return fail(TF_EINVAL, "NULL argument");
+    TRY(refresh_working(f));
+    if (!f->exec || f->g_params != params || f->g_out != out || f->g_batch != batch) {
+        if (f->exec) {
+            TF_HIP(hipStreamSynchronize(f->st));
+            TF_HIP(hipGraphExecDestroy(f->exec));
+            f->exec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        TF_HIP(hipStreamBeginCapture(f->cap, hipStreamCaptureModeThreadLocal));
+        f->cur = f->cap;
+        const tf_status st = forward_body(f, params, batch, out);
+        f->cur = f->st;
+        const hipError_t e = hipStreamEndCapture(f->cap, &graph);
+        if (st != TF_OK || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st != TF_OK ? st : fail(TF_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        }
+        const hipError_t e2 = hipGraphInstantiate(&f->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e2 != hipSuccess) {
+            f->exec = nullptr;
+            return fail(TF_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e2));
+        }
+        f->g_params = params;
+        f->g_out = out;
+        f->g_batch = batch;
+    }
+    TF_HIP(hipGraphLaunch(f->exec, f->st));
+    return TF_OK;
+}
+
 tf_status tf_fno_loss_grad(tf_fno* f, const float* params, const float* target, int32_t batch, double* loss,
                            float* grad) {
     TRY(check_batch(f, batch));
@@ -1098,7 +1146,7 @@ tf_status tf_fno_train_step(tf_fno* f, const float* params, const float* target,
     f->adam_t += 1;
     const double b1 = 0.9, b2 = 0.999;
     const float bc1 = float(1.0 - std::pow(b1, double(f->adam_t))), bc2 = float(1.0 - std::pow(b2, double(f->adam_t)));
-    hipLaunchKernelGGL(k_adam, dim3((NPARAMS + 255) / 256), dim3(256), 0, f->st, f->prm, f->am, f->av, f->grad,
+    hipLaunchKernelGGL(k_adam, dim3((NPARAMS + 255) / 256), dim3(256), 0, f->cur, f->prm, f->am, f->av, f->grad,
                        NPARAMS, float(lr), float(b1), float(b2), 1e-8f, bc1, bc2);
     TRY(launched());
     f->working_stale = true;
@@ -1125,7 +1173,7 @@ tf_status tf_fno_spectral_inverse(tf_fno* f, const float* modes, int32_t batch, 
     TRY(run(f, g_zexpand(f->gs, modes, f->T2, batch), 128 * 48, nb * X3_SZ, nb * X2_SZ));
     TRY(run(f, g_yexpand(f->gs, f->T2, f->T1, batch), 128 * 48, nb * X2_SZ, nb * X1_SZ));
     LineArgs a{f->gx, f->T1, nullptr, f->wb[0], nullptr, nullptr, nullptr, u, batch * N * N, 0, 0};
-    hipLaunchKernelGGL(k_lineout, dim3((batch * N * N + 3) / 4), dim3(256), 0, f->st, a);
+    hipLaunchKernelGGL(k_lineout, dim3((batch * N * N + 3) / 4), dim3(256), 0, f->cur, a);
     return launched();
 }
 

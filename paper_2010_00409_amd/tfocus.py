@@ -97,6 +97,7 @@ _SIGS = {
     "tf_fno_set_params": ([_P, _P, ctypes.c_int32], ctypes.c_int),
     "tf_fno_get_params": ([_P, _P, ctypes.c_int32], ctypes.c_int),
     "tf_fno_forward": ([_P, _P, ctypes.c_int32, _P], ctypes.c_int),
+    "tf_fno_infer": ([_P, _P, ctypes.c_int32, _P], ctypes.c_int),
     "tf_fno_loss_grad": ([_P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
     "tf_fno_train_step": ([_P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)],
                           ctypes.c_int),
@@ -554,11 +555,13 @@ class Surrogate:
         _check(load().tf_fno_get_params(self.h, flat.ctypes.data, 0))
         return flat
 
-    def forward(self, p, out):
+    def forward(self, p, out, graph=False):
+        """out <- surrogate(p); graph=True replays a captured hipGraph."""
         B = p.shape[0]
         pp = self._dev(p, (B, FNO_NPARAM), "params")
         po = self._dev(out, (B, FNO_NOUT, FNO_N, FNO_N, FNO_N), "out")
-        _check(load().tf_fno_forward(self.h, pp, B, po))
+        fn = load().tf_fno_infer if graph else load().tf_fno_forward
+        _check(fn(self.h, pp, B, po))
         return out
 
     def loss_grad(self, p, target, want_grad=True):

@@ -162,3 +162,26 @@ def test_adam_steps_reduce_the_loss_and_checkpoint_roundtrips(tmp_path):
         assert np.array_equal(s.get_params(), flat)
         assert s.train_step(pd, yd, 1e-3) == nxt            # Adam state restored too
     assert losses[-1] < 0.7 * losses[0], losses
+
+
+def test_graph_inference_replays_equal_eager_forward():
+    """tf_fno_infer captures the forward pass once and replays it; every
+    replay (with eager work in between, and after new parameters) must equal
+    the eager forward bit for bit."""
+    pb = torch.from_numpy(np.random.default_rng(15).uniform(size=(3, 8)).astype(np.float32)).cuda()
+    shape = (3, 6, 64, 64, 64)
+    out = torch.empty(shape, dtype=torch.float32, device="cuda")
+    with tf.Surrogate(4) as s:
+        for seed in (13, 14):
+            s.set_params(make_params(seed))
+            ref = torch.zeros(shape, dtype=torch.float32, device="cuda")
+            s.forward(pb, ref)
+            torch.cuda.synchronize()
+            for _ in range(3):
+                out.fill_(float("nan"))
+                s.forward(pb, out, graph=True)
+                torch.cuda.synchronize()
+                junk = torch.randn(1 << 20, device="cuda").sum()
+                torch.cuda.synchronize()
+                del junk
+                assert torch.equal(out, ref)

@@ -283,29 +283,50 @@ tf_status tf_tune(const int32_t* sizes, int32_t n, int32_t precision, const char
  *   v_{l+1} = GELU(z_l) except after the last layer;
  * kept modes kx in [0, 12), ky, kz in [0, 12) U [52, 64), mode
  * q = (kz_i * 24 + ky_i) * 12 + kx (i: position in the kept list); R_l[q] a
- * complex 32 x 32 matrix; projection GELU(v P1 + c1) P2 + c2 to 6 outputs.
+ * complex 32 x 32 matrix; projection o = GELU(v P1 + c1) P2 + c2 to 6 K
+ * channels (K basis fields of 6 components) and the output
+ * out = sum_k w[k] o[6k .. 6k + 5] with per-sample head weights w.
+ * K = 1 (w = 1) is the plain head.  K = 2 and K = 4 use the solver's
+ * linearity: the initial field, hence the focal field, is
+ * Re[exp(i s CEP) F] / gnorm with a complex F (s = +1 for the spectral
+ * envelope, -1 for the sin(k z - CEP) envelopes of Eq. (7) and Sec. III.B.1;
+ * gnorm the spectral normalisation), so K = 2 learns Re F and Im F and takes
+ * the carrier-envelope phase exactly; K = 4 learns F for polarisation along y
+ * and along z and weights them by the polarisation angle and ellipticity
+ * (exact on the optical axis, where the direction factor of Sec. II.B is
+ * linear in d; the network corrects the rest).  tf_fno_phasor_weights gives w.
  * Loss: mean over the batch of ||out - y|| / ||y||.
  *
- * Parameters are one float32 vector of tf_fno_param_count() entries:
+ * Parameters are one float32 vector of tf_fno_param_count(K) entries:
  * W0 (11 x 32), b0 (32), then for each layer W (32 x 32), b (32),
  * R (6912 x 32 x 32 complex stored [q][c][o][re, im]), then P1 (32 x 128),
- * c1 (128), P2 (128 x 6), c2 (6); matrices row-major, input index first.
+ * c1 (128), P2 (128 x 6K), c2 (6K); matrices row-major, input index first.
  * Every contraction runs on bf16 MFMA with float32 accumulation; learned
  * weights are used as bf16 copies of the float32 master weights.
  *
- * Device layouts: params [B][8]; out and target [B][6][64][64][64]
- * (components Ex Ey Ez Bx By Bz, x fastest); node tensors v, u
- * [B][64 z][64 y][64 x][32 c]; modes [B][24 kz][2 re/im][24 ky][12 kx][32 c]. */
+ * Device layouts: params [B][8]; head_w [B][K] (NULL allowed when K = 1);
+ * out and target [B][6][64][64][64] (components Ex Ey Ez Bx By Bz, x
+ * fastest); node tensors v, u [B][64 z][64 y][64 x][32 c]; modes
+ * [B][24 kz][2 re/im][24 ky][12 kx][32 c]. */
 
 typedef struct tf_fno tf_fno;
 
-int64_t tf_fno_param_count(void);
+/* Parameter count for a head of nbasis (1, 2 or 4) basis fields; -1 otherwise. */
+int64_t tf_fno_param_count(int32_t nbasis);
 
-/* Allocate a surrogate for batches up to max_batch (1..128) on the current
- * device.  training = 0 allocates only what inference needs (about
- * 80 MB per sample); training = 1 also keeps activations, gradients and Adam
- * state (about 0.45 GB per sample plus 0.8 GB).  Parameters start at 0. */
-tf_status tf_fno_create(int32_t max_batch, int32_t training, void* hip_stream, tf_fno** out);
+/* Host only.  Head weights w[0..nbasis) of a pulse: nbasis 1: {1}; 2:
+ * {Re z, -Im z} / gnorm; 4: {Re za, -Im za, Re zb, -Im zb} / gnorm with
+ * z = exp(i s CEP), a = (cos psi - i s e sin psi) / n, b = (sin psi + i s e cos psi) / n,
+ * n = sqrt(1 + e^2), psi the polarisation angle and e the ellipticity
+ * (radial polarisation: a = 1, b = 0). */
+tf_status tf_fno_phasor_weights(const tf_pulse* pulse, int32_t nbasis, double* w);
+
+/* Allocate a surrogate for batches up to max_batch (1..128) with a head of
+ * nbasis basis fields on the current device.  training = 0 allocates only
+ * what inference needs (about 80 MB per sample); training = 1 also keeps
+ * activations, gradients and Adam state (about 0.45 GB per sample plus
+ * 0.8 GB).  Parameters start at 0. */
+tf_status tf_fno_create(int32_t max_batch, int32_t training, int32_t nbasis, void* hip_stream, tf_fno** out);
 tf_status tf_fno_destroy(tf_fno* f);
 
 /* Copy the flat parameter vector in or out.  Setting resets Adam. */
@@ -314,26 +335,26 @@ tf_status tf_fno_get_params(tf_fno* f, float* dst, int32_t dst_on_device);
 
 /* Inference: out <- surrogate(params) for batch samples (device pointers).
  * Asynchronous on the surrogate's stream. */
-tf_status tf_fno_forward(tf_fno* f, const float* params, int32_t batch, float* out);
+tf_status tf_fno_forward(tf_fno* f, const float* params, const float* head_w, int32_t batch, float* out);
 
 /* Inference as one graph replay: the whole forward pass is captured into a
- * hipGraph on first use and replayed while params, out and batch are the
- * same pointers and size (new parameter values are picked up; their bf16
- * working copies are refreshed before the replay).  Results equal
- * tf_fno_forward bit for bit.  Asynchronous on the surrogate's stream. */
-tf_status tf_fno_infer(tf_fno* f, const float* params, int32_t batch, float* out);
+ * hipGraph on first use and replayed while params, head_w, out and batch are
+ * the same pointers and size (new values in them, and new parameters, are
+ * picked up; bf16 working copies are refreshed before the replay).  Results
+ * equal tf_fno_forward bit for bit.  Asynchronous on the surrogate's stream. */
+tf_status tf_fno_infer(tf_fno* f, const float* params, const float* head_w, int32_t batch, float* out);
 
-/* Loss and gradient of the batch (device params and target).  loss (host,
- * nullable) receives the loss; grad (host, nullable) receives the gradient in
- * the flat parameter layout.  Either pointer synchronises.  TF_ESTATE for an
- * inference-only surrogate. */
-tf_status tf_fno_loss_grad(tf_fno* f, const float* params, const float* target, int32_t batch, double* loss,
-                           float* grad);
+/* Loss and gradient of the batch (device params, head weights and target).
+ * loss (host, nullable) receives the loss; grad (host, nullable) receives the
+ * gradient in the flat parameter layout.  Either pointer synchronises.
+ * TF_ESTATE for an inference-only surrogate. */
+tf_status tf_fno_loss_grad(tf_fno* f, const float* params, const float* head_w, const float* target, int32_t batch,
+                           double* loss, float* grad);
 
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with
  * learning rate lr on the batch loss.  loss (host, nullable) as above. */
-tf_status tf_fno_train_step(tf_fno* f, const float* params, const float* target, int32_t batch, double lr,
-                            double* loss);
+tf_status tf_fno_train_step(tf_fno* f, const float* params, const float* head_w, const float* target,
+                            int32_t batch, double lr, double* loss);
 
 /* The operator's truncated transforms on their own (device pointers):
  * modes <- rfft3(v) on the kept modes; u <- irfft3 of the kept modes with
@@ -343,7 +364,7 @@ tf_status tf_fno_spectral_inverse(tf_fno* f, const float* modes, int32_t batch, 
 
 /* Checkpoint the float32 parameters (and, for a training surrogate, the Adam
  * moments and step) to a file, and read one back.  TF_EINVAL for a file of
- * another architecture. */
+ * another architecture or head. */
 tf_status tf_fno_save(tf_fno* f, const char* path);
 tf_status tf_fno_load(tf_fno* f, const char* path);
 

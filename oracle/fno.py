@@ -16,7 +16,12 @@ Definition (one sample; x runs over the N^3 window nodes):
     z_l   = u + v_l W_l + b_l
     v_l+1 = GELU(z_l) for l < L-1, z_L-1 for the last layer
   h       = GELU(v_L P1 + c1)                           (hidden H)
-  out     = h P2 + c2                                   (6 field components)
+  o       = h P2 + c2                                   (6 K channels)
+  out     = sum_k w[k] o[6k : 6k + 6]                   (6 field components)
+With K = 1 and w = 1 (the plain head) out = o.  With K = 4 (the phasor head)
+the channels are the real and imaginary parts of two complex basis fields and
+w holds, per sample, the exact weights of the pulse's carrier phase and
+polarisation (oracle.pulse.phasor_weights).
 Kept modes: kx in [0, M) on the rfft axis, ky and kz in [0, M) U [N-M, N)
 (the usual truncation; the set is not closed under negation, so in the
 kx = 0 plane the index N-M has no kept partner).
@@ -32,9 +37,10 @@ import scipy.special
 
 
 class HP:
-    def __init__(self, n=64, width=32, modes=12, nparam=8, hidden=128, nout=6, layers=3):
+    def __init__(self, n=64, width=32, modes=12, nparam=8, hidden=128, nout=6, layers=3, nbasis=1):
         self.n, self.width, self.modes = n, width, modes
         self.nparam, self.hidden, self.nout, self.layers = nparam, hidden, nout, layers
+        self.nbasis = nbasis
 
     @property
     def nmodes(self):
@@ -61,7 +67,7 @@ def init_params(seed, hp):
     nin = hp.nparam + 3
     P = {"W0": rng.normal(0, 1 / math.sqrt(nin), (nin, C)), "b0": np.zeros(C),
          "P1": rng.normal(0, 1 / math.sqrt(C), (C, H)), "c1": np.zeros(H),
-         "P2": rng.normal(0, 1 / math.sqrt(H), (H, hp.nout)), "c2": np.zeros(hp.nout)}
+         "P2": rng.normal(0, 1 / math.sqrt(H), (H, hp.nout * hp.nbasis)), "c2": np.zeros(hp.nout * hp.nbasis)}
     scale = 1.0 / (C * C)
     for l in range(hp.layers):
         P[f"W{l + 1}"] = rng.normal(0, 1 / math.sqrt(C), (C, C))
@@ -121,7 +127,16 @@ def _outer(x, g):
     return np.einsum("bis,bos->io", x.reshape(B, x.shape[1], -1), g.reshape(B, g.shape[1], -1))
 
 
-def forward(P, pb, hp, keep=False):
+def _weights(w, B, hp):
+    if w is None:
+        assert hp.nbasis == 1
+        return np.ones((B, 1))
+    w = np.asarray(w, dtype=np.float64)
+    assert w.shape == (B, hp.nbasis)
+    return w
+
+
+def forward(P, pb, hp, keep=False, w=None):
     cache = {}
     a = inputs(pb, hp)
     v = _pw(a, P["W0"], P["b0"])
@@ -139,7 +154,10 @@ def forward(P, pb, hp, keep=False):
     cache["hpre"] = hpre
     h = gelu(hpre)
     cache["h"] = h
-    out = _pw(h, P["P2"], P["c2"])
+    o = _pw(h, P["P2"], P["c2"])
+    w = _weights(w, o.shape[0], hp)
+    out = np.einsum("bk,bkc...->bc...", w, o.reshape((o.shape[0], hp.nbasis, hp.nout) + o.shape[2:]))
+    cache["w"] = w
     return (out, cache) if keep else out
 
 
@@ -149,14 +167,16 @@ def loss(out, y):
     return float(np.mean(np.linalg.norm(d, axis=1) / np.linalg.norm(y.reshape(B, -1), axis=1)))
 
 
-def loss_and_grad(P, pb, y, hp):
-    out, c = forward(P, pb, hp, keep=True)
+def loss_and_grad(P, pb, y, hp, w=None):
+    out, c = forward(P, pb, hp, keep=True, w=w)
     B = out.shape[0]
     d = (out - y).reshape(B, -1)
     nd = np.linalg.norm(d, axis=1)
     ny = np.linalg.norm(y.reshape(B, -1), axis=1)
     L = float(np.mean(nd / ny))
     g_out = (d / (B * nd[:, None] * ny[:, None])).reshape(out.shape)
+    # the head's weights spread dL/dout over the K basis channel groups
+    g_out = np.einsum("bk,bc...->bkc...", c["w"], g_out).reshape((B, hp.nbasis * hp.nout) + out.shape[2:])
     G = {}
     G["P2"] = _outer(c["h"], g_out)
     G["c2"] = g_out.sum(axis=(0, 2, 3, 4))

@@ -174,6 +174,45 @@ def pol_parts(p):
     return parts
 
 
+def phasor_weights(p, nbasis):
+    """Per-pulse weights of the surrogate's basis fields.
+
+    Every envelope is u_l(zeta; phase) = Re[exp(i sigma phase) G(zeta)] with
+    sigma = +1 for the spectral envelope (its phase enters as +phase) and -1
+    for the cos^2 and Gaussian envelopes (sin(k zeta - phase), Eq. (7)); the
+    spectral one is divided by gnorm (Q17), the others by 1.  The polarisation
+    parts are (1/n) d1 at phase CEP and (e/n) d2 at CEP + pi/2, n = sqrt(1+e^2).
+    Since the solver is linear, with z = exp(i sigma CEP):
+      nbasis 1: [1]                                          (plain output)
+      nbasis 2: [Re z, -Im z] / gnorm  -- weights of Re F, Im F, where F is the
+                complex field of the same pulse at CEP = 0, gnorm = 1.  Exact.
+      nbasis 4: [Re(z a), -Im(z a), Re(z b), -Im(z b)] / gnorm, the weights of
+                Re F_y, Im F_y, Re F_z, Im F_z (d along y, z; CEP = 0; gnorm = 1)
+                with a = (cos psi - i sigma e sin psi) / n, b = (sin psi + i sigma e cos psi) / n.
+                Exact where the direction factor R x (d x R) / |R x (d x R)|
+                is linear in d (on the optical axis); elsewhere its
+                normalisation adds a polarisation-dependent correction.
+    Radial polarisation: a = 1, b = 0."""
+    if nbasis == 1:
+        return np.ones(1)
+    sig = 1.0 if p["envelope"] == "spectral" else -1.0
+    gn = spectral_norm(p) if p["envelope"] == "spectral" else 1.0
+    z = complex(math.cos(sig * p["cep"]), math.sin(sig * p["cep"]))
+    if nbasis == 2:
+        return np.array([z.real, -z.imag]) / gn
+    if nbasis != 4:
+        raise ValueError("nbasis must be 1, 2 or 4")
+    if p["polarization"] == "radial":
+        a, b = 1.0 + 0j, 0j
+    else:
+        psi, e = p.get("pol_angle", 0.0), p.get("ellipticity", 0.0)
+        n = math.sqrt(1.0 + e * e)
+        a = complex(math.cos(psi), -sig * e * math.sin(psi)) / n
+        b = complex(math.sin(psi), sig * e * math.cos(psi)) / n
+    za, zb = z * a, z * b
+    return np.array([za.real, -za.imag, zb.real, -zb.imag]) / gn
+
+
 def fields_at(x, y, z, p, g, gnorm=None):
     """E, B (each a (3, ...) array) of the unmapped pulse at points."""
     x, y, z = (np.asarray(v, dtype=np.float64) for v in (x, y, z))

@@ -52,7 +52,8 @@ constexpr int NCHUNK = N3 / CHUNK;
 
 // Flat parameter vector (fp32): W0 (11x32), b0, then per layer W (32x32),
 // b (32), R (NMODES x 32 x 32 complex as [q][c][o][re, im]), then P1 (32x128),
-// c1, P2 (128x6), c2.  Row-major, input index first.
+// c1, P2 (128 x 6K), c2 (6K) for a head of K basis fields.  Row-major, input
+// index first.
 constexpr int64_t OFF_W0 = 0, OFF_B0 = 11 * C;
 constexpr int64_t LAYER_SZ = C * C + C + int64_t(NMODES) * C * C * 2;
 constexpr int64_t OFF_L0 = OFF_B0 + C;
@@ -62,8 +63,8 @@ constexpr int64_t off_r(int l) { return off_b(l) + C; }
 constexpr int64_t OFF_P1 = OFF_L0 + LAYERS * LAYER_SZ;
 constexpr int64_t OFF_C1 = OFF_P1 + C * HID;
 constexpr int64_t OFF_P2 = OFF_C1 + HID;
-constexpr int64_t OFF_C2 = OFF_P2 + HID * NOUT;
-constexpr int64_t NPARAMS = OFF_C2 + NOUT;
+constexpr int64_t off_c2(int nb) { return OFF_P2 + int64_t(HID) * NOUT * nb; }
+constexpr int64_t nparams(int nb) { return off_c2(nb) + NOUT * nb; }
 
 typedef __bf16 bf16;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
@@ -321,8 +322,8 @@ struct ProjArgs {
     const float* v;       // [B][N3][32]
     const bf16* p1;       // [32][128]
     const float* c1;      // [128]
-    const bf16* p2;       // [128][6]
-    const float* c2;      // [6]
+    const bf16* p2;       // [B][128][6]: the head's effective projection per sample
+    const float* c2;      // [B][6]
     float* out;           // forward: [B][6][N3]
     const float* gout;    // backward: dL/dout [B][6][N3]
     float* gv;            // backward: [B][N3][32]
@@ -362,6 +363,8 @@ __global__ __launch_bounds__(256) void k_proj(ProjArgs a) {
         }
     }
 
+    const bf16* p2 = a.p2 + int64_t(b) * HID * NOUT;
+    const float* c2 = a.c2 + b * NOUT;
     if (!a.bwd) {
         f32x16 oacc;
 #pragma unroll
@@ -380,7 +383,7 @@ __global__ __launch_bounds__(256) void k_proj(ProjArgs a) {
                 for (int e = 0; e < 8; ++e) {
                     const int hd = 32 * mt + kappa(s, grp, e);
                     hf[e] = (bf16)gelu(acc[8 * s + e] + a.c1[hd]);
-                    pf[e] = t < NOUT ? a.p2[hd * NOUT + t] : (bf16)0.0f;
+                    pf[e] = t < NOUT ? p2[hd * NOUT + t] : (bf16)0.0f;
                 }
                 oacc = mfma(pf, hf, oacc);
             }
@@ -390,7 +393,7 @@ __global__ __launch_bounds__(256) void k_proj(ProjArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int o = 4 * grp + r;
-            if (o < NOUT) op[int64_t(o) * N3] = oacc[r] + a.c2[o];
+            if (o < NOUT) op[int64_t(o) * N3] = oacc[r] + c2[o];
         }
         return;
     }
@@ -421,7 +424,7 @@ __global__ __launch_bounds__(256) void k_proj(ProjArgs a) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int o = 8 * grp + e;
-            p2f[e] = o < NOUT ? a.p2[(32 * mt + t) * NOUT + o] : (bf16)0.0f;
+            p2f[e] = o < NOUT ? p2[(32 * mt + t) * NOUT + o] : (bf16)0.0f;
         }
         gacc = mfma(p2f, gf, gacc);
 #pragma unroll
@@ -557,13 +560,14 @@ __global__ void k_gout(const float* out, const float* y, const double* res, floa
     g[i] = float(double(out[i] - y[i]) * res[1 + b]);
 }
 
-// dst[e] = sum_p part[p * len + e], in a fixed order
+// dst[y][e] = sum_p part[y][p][e] (y = blockIdx.y), in a fixed order
 __global__ void k_reduce(const float* part, int nparts, int len, float* dst) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= len) return;
+    const float* src = part + int64_t(blockIdx.y) * nparts * len;
     float s = 0;
-    for (int p = 0; p < nparts; ++p) s += part[int64_t(p) * len + e];
-    dst[e] = s;
+    for (int p = 0; p < nparts; ++p) s += src[int64_t(p) * len + e];
+    dst[int64_t(blockIdx.y) * len + e] = s;
 }
 
 // dL/dR from the real 64x64 block gradient G* of Y* = X* R*:
@@ -588,6 +592,33 @@ __global__ void k_expand_r(const float* r, bf16* rb) {
     const float* e = r + ((q * C + c) * C + o) * 2;
     const float v = s == s2 ? e[0] : (s == 0 ? e[1] : -e[1]);
     rb[i] = (bf16)v;
+}
+
+// Effective projection of sample b for a head of nb basis fields:
+//   P2eff[b][hd][c] = sum_k w[b][k] P2[hd][6k + c],  c2eff[b][c] = sum_k w[b][k] c2[6k + c]
+// (w = 1 when nb = 1 and no weights are given).
+__global__ void k_head_eff(const float* p2, const float* c2, const float* w, int nb, int B, bf16* p2e, float* c2e) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = (HID + 1) * NOUT;
+    if (i >= B * per) return;
+    const int b = i / per, r = (i % per) / NOUT, c = i % NOUT;
+    const float* src = r < HID ? p2 + int64_t(r) * NOUT * nb : c2;
+    float s = 0.0f;
+    for (int k = 0; k < nb; ++k) s += (w ? w[b * nb + k] : 1.0f) * src[NOUT * k + c];
+    if (r < HID) p2e[(int64_t(b) * HID + r) * NOUT + c] = (bf16)s;
+    else c2e[b * NOUT + c] = s;
+}
+
+// dL/dP2 and dL/dc2 from the per-sample gradients of the effective head
+// (geff [B][129][6], row 128 the bias):  G[r][6k + c] = sum_b w[b][k] geff[b][r][c]
+__global__ void k_head_grad(const float* geff, const float* w, int nb, int B, float* g) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int cols = NOUT * nb;
+    if (i >= (HID + 1) * cols) return;
+    const int r = i / cols, col = i % cols, k = col / NOUT, c = col % NOUT;
+    float s = 0.0f;
+    for (int b = 0; b < B; ++b) s += (w ? w[b * nb + k] : 1.0f) * geff[(int64_t(b) * (HID + 1) + r) * NOUT + c];
+    g[int64_t(r) * cols + col] = s;
 }
 
 __global__ void k_to_bf16(const float* src, bf16* dst, int n) {
@@ -724,13 +755,17 @@ struct tf_fno {
     float* g_out = nullptr;
     int g_batch = 0;
     int maxB = 0;
+    int nb = 1;                 // basis fields of the output head
+    int64_t np = 0;             // parameter count
+    const float* g_w = nullptr;
     bool training = false;
     int64_t adam_t = 0;
     bool working_stale = true;
 
     std::vector<void*> allocs;
     float *prm = nullptr, *grad = nullptr, *am = nullptr, *av = nullptr;
-    bf16 *wb[LAYERS] = {}, *rb[LAYERS] = {}, *p1b = nullptr, *p2b = nullptr, *zero_w = nullptr;
+    bf16 *wb[LAYERS] = {}, *rb[LAYERS] = {}, *p1b = nullptr, *p2e = nullptr;
+    float *c2e = nullptr, *geff = nullptr;
     float *fx, *fxT, *gx, *gxT, *fs, *fsT, *gs, *gsT;
     float* V[4] = {};
     float* Z[2] = {};
@@ -847,13 +882,54 @@ Gemm g_mix_grad(const float* X, const float* gY, float* gs, int B) {
 
 extern "C" {
 
-int64_t tf_fno_param_count(void) { return NPARAMS; }
+int64_t tf_fno_param_count(int32_t nbasis) {
+    return (nbasis == 1 || nbasis == 2 || nbasis == 4) ? nparams(nbasis) : -1;
+}
 
-tf_status tf_fno_create(int32_t max_batch, int32_t training, void* hip_stream, tf_fno** out) {
+tf_status tf_fno_phasor_weights(const tf_pulse* pulse, int32_t nbasis, double* w) {
+    if (!w) return fail(TF_EINVAL, "w is NULL");
+    if (nbasis != 1 && nbasis != 2 && nbasis != 4) return fail(TF_EINVAL, "nbasis must be 1, 2 or 4");
+    TRY(tf::host::validate_pulse(pulse));
+    if (nbasis == 1) {
+        w[0] = 1.0;
+        return TF_OK;
+    }
+    // envelope Re[exp(i sig phase) G]: sig = +1 spectral, -1 for the sin(k z - phase) envelopes
+    const double sig = pulse->envelope == TF_ENV_SPECTRAL ? 1.0 : -1.0;
+    double gnorm = 1.0;
+    if (pulse->envelope == TF_ENV_SPECTRAL) {
+        std::vector<double> tab;
+        tf::host::spectral_table(pulse, tab, gnorm);
+        if (!(gnorm > 0.0)) return fail(TF_EINVAL, "spectral pulse vanishes in its window");
+    }
+    const double zr = std::cos(sig * pulse->cep), zi = std::sin(sig * pulse->cep);
+    if (nbasis == 2) {
+        w[0] = zr / gnorm;
+        w[1] = -zi / gnorm;
+        return TF_OK;
+    }
+    double ar = 1.0, ai = 0.0, br = 0.0, bi = 0.0;
+    if (pulse->polarization == TF_POL_LINEAR) {
+        const double e = pulse->ellipticity, n = std::sqrt(1.0 + e * e);
+        const double c = std::cos(pulse->pol_angle), s = std::sin(pulse->pol_angle);
+        ar = c / n; ai = -sig * e * s / n;
+        br = s / n; bi = sig * e * c / n;
+    }
+    w[0] = (zr * ar - zi * ai) / gnorm;     // Re(z a)
+    w[1] = -(zr * ai + zi * ar) / gnorm;    // -Im(z a)
+    w[2] = (zr * br - zi * bi) / gnorm;
+    w[3] = -(zr * bi + zi * br) / gnorm;
+    return TF_OK;
+}
+
+tf_status tf_fno_create(int32_t max_batch, int32_t training, int32_t nbasis, void* hip_stream, tf_fno** out) {
     if (!out) return fail(TF_EINVAL, "out is NULL");
     *out = nullptr;
     if (max_batch < 1 || max_batch > 128) return fail(TF_EINVAL, "max_batch must be in [1, 128]");
+    if (nbasis != 1 && nbasis != 2 && nbasis != 4) return fail(TF_EINVAL, "nbasis must be 1, 2 or 4");
     std::unique_ptr<tf_fno> f(new tf_fno());
+    f->nb = nbasis;
+    f->np = nparams(nbasis);
     f->maxB = max_batch;
     f->training = training != 0;
     f->st = (hipStream_t)hip_stream;
@@ -862,6 +938,7 @@ tf_status tf_fno_create(int32_t max_batch, int32_t training, void* hip_stream, t
     TF_HIP(hipStreamCreateWithFlags(&f->cap, hipStreamNonBlocking));
     const int64_t B = max_batch;
 
+    const int64_t NPARAMS = f->np;
     TRY(f->alloc(&f->prm, NPARAMS));
     TF_HIP(hipMemset(f->prm, 0, NPARAMS * sizeof(float)));
     for (int l = 0; l < LAYERS; ++l) {
@@ -869,7 +946,8 @@ tf_status tf_fno_create(int32_t max_batch, int32_t training, void* hip_stream, t
         TRY(f->alloc(&f->rb[l], int64_t(NMODES) * 4096));
     }
     TRY(f->alloc(&f->p1b, C * HID));
-    TRY(f->alloc(&f->p2b, HID * NOUT));
+    TRY(f->alloc(&f->p2e, B * HID * NOUT));
+    TRY(f->alloc(&f->c2e, B * NOUT));
 
     Tables t = build_tables();
     float* tab = nullptr;
@@ -913,6 +991,7 @@ tf_status tf_fno_create(int32_t max_batch, int32_t training, void* hip_stream, t
         TRY(f->alloc(&f->ghT, B * HID * N3));
         TRY(f->alloc(&f->part, B * NCHUNK * 33 * HID));
         TRY(f->alloc(&f->gstar, int64_t(NMODES) * 4096));
+        TRY(f->alloc(&f->geff, B * (HID + 1) * NOUT));
     }
     TF_HIP(hipDeviceSynchronize());
     *out = f.release();
@@ -937,8 +1016,6 @@ tf_status refresh_working(tf_fno* f) {
         hipLaunchKernelGGL(k_expand_r, dim3((n + 255) / 256), dim3(256), 0, f->cur, f->prm + off_r(l), f->rb[l]);
     }
     hipLaunchKernelGGL(k_to_bf16, dim3((C * HID + 255) / 256), dim3(256), 0, f->cur, f->prm + OFF_P1, f->p1b, C * HID);
-    hipLaunchKernelGGL(k_to_bf16, dim3((HID * NOUT + 255) / 256), dim3(256), 0, f->cur, f->prm + OFF_P2, f->p2b,
-                       HID * NOUT);
     TRY(launched());
     f->working_stale = false;
     return TF_OK;
@@ -946,8 +1023,13 @@ tf_status refresh_working(tf_fno* f) {
 
 // Forward pass.  Training keeps v_l, z_l and the modes of every layer for the
 // backward pass; inference ping-pongs two node tensors.
-tf_status forward_body(tf_fno* f, const float* params, int B, float* out) {
+tf_status forward_body(tf_fno* f, const float* params, const float* hw, int B, float* out) {
     const int64_t nb = B;
+    {
+        const int n = B * (HID + 1) * NOUT;
+        hipLaunchKernelGGL(k_head_eff, dim3((n + 255) / 256), dim3(256), 0, f->cur, f->prm + OFF_P2,
+                           f->prm + off_c2(f->nb), hw, f->nb, B, f->p2e, f->c2e);
+    }
     {
         const int64_t tot = nb * NODE_SZ;
         hipLaunchKernelGGL(k_lift, dim3((tot + 255) / 256), dim3(256), 0, f->cur, params, f->prm + OFF_W0,
@@ -971,24 +1053,24 @@ tf_status forward_body(tf_fno* f, const float* params, int B, float* out) {
         TRY(launched());
         v = nv;
     }
-    ProjArgs p{v, f->p1b, f->prm + OFF_C1, f->p2b, f->prm + OFF_C2, out, nullptr, nullptr, nullptr, nullptr,
+    ProjArgs p{v, f->p1b, f->prm + OFF_C1, f->p2e, f->c2e, out, nullptr, nullptr, nullptr, nullptr,
                B * (N3 / 32), 0};
     hipLaunchKernelGGL(k_proj, dim3((p.ntiles + 3) / 4), dim3(256), 0, f->cur, p);
     return launched();
 }
 
-tf_status forward(tf_fno* f, const float* params, int B, float* out) {
+tf_status forward(tf_fno* f, const float* params, const float* hw, int B, float* out) {
     TRY(refresh_working(f));
-    return forward_body(f, params, B, out);
+    return forward_body(f, params, hw, B, out);
 }
 
 // split-K weight gradient [A | 1]^T-style reductions into the flat gradient
-tf_status reduce_into(tf_fno* f, int nparts, int len, float* dst) {
-    hipLaunchKernelGGL(k_reduce, dim3((len + 255) / 256), dim3(256), 0, f->cur, f->part, nparts, len, dst);
+tf_status reduce_into(tf_fno* f, int nparts, int len, float* dst, int groups = 1) {
+    hipLaunchKernelGGL(k_reduce, dim3((len + 255) / 256, groups), dim3(256), 0, f->cur, f->part, nparts, len, dst);
     return launched();
 }
 
-tf_status backward(tf_fno* f, const float* params, const float* target, int B) {
+tf_status backward(tf_fno* f, const float* params, const float* hw, const float* target, int B) {
     const int64_t nb = B;
     const int64_t szN = nb * NODE_SZ, sz1 = nb * X1_SZ, sz2 = nb * X2_SZ, sz3 = nb * X3_SZ;
     const int64_t szO = nb * OUT_SZ, szH = nb * HID * N3, szP = nb * NCHUNK * 33 * HID;
@@ -999,7 +1081,7 @@ tf_status backward(tf_fno* f, const float* params, const float* target, int B) {
     TRY(launched());
     // projection
     float* g = f->G[0];
-    ProjArgs p{f->V[3], f->p1b, f->prm + OFF_C1, f->p2b, f->prm + OFF_C2, nullptr, f->gout, g, f->hT, f->ghT,
+    ProjArgs p{f->V[3], f->p1b, f->prm + OFF_C1, f->p2e, f->c2e, nullptr, f->gout, g, f->hT, f->ghT,
                B * (N3 / 32), 1};
     hipLaunchKernelGGL(k_proj, dim3((p.ntiles + 3) / 4), dim3(256), 0, f->cur, p);
     TRY(launched());
@@ -1015,7 +1097,12 @@ tf_status backward(tf_fno* f, const float* params, const float* target, int B) {
                    opnd(f->gout, plain(1), plain(N3), CHUNK, OUT_SZ, 1),
                    res(f->part, plain(NOUT), plain(1), 129 * NOUT, int64_t(NCHUNK) * 129 * NOUT), 129, NOUT, CHUNK};
         TRY(run(f, Gemm{a, NCHUNK, B, launch<32, 32, 1, bf16, float, false>}, szH, szO, szP));
-        TRY(reduce_into(f, B * NCHUNK, 129 * NOUT, f->grad + OFF_P2));
+        // per-sample gradient of the effective head, then through the head weights
+        TRY(reduce_into(f, NCHUNK, 129 * NOUT, f->geff, B));
+        const int n = (HID + 1) * NOUT * f->nb;
+        hipLaunchKernelGGL(k_head_grad, dim3((n + 255) / 256), dim3(256), 0, f->cur, f->geff, hw, f->nb, B,
+                           f->grad + OFF_P2);
+        TRY(launched());
     }
     for (int l = LAYERS - 1; l >= 0; --l) {
         float* gn = g == f->G[0] ? f->G[1] : f->G[0];
@@ -1051,9 +1138,10 @@ tf_status backward(tf_fno* f, const float* params, const float* target, int B) {
     return launched();
 }
 
-tf_status check_batch(tf_fno* f, int B) {
+tf_status check_batch(tf_fno* f, int B, const float* hw, bool need_w = true) {
     if (!f) return fail(TF_EINVAL, "surrogate is NULL");
     if (B < 1 || B > f->maxB) return fail(TF_EINVAL, "batch must be in [1, max_batch]");
+    if (need_w && !hw && f->nb != 1) return fail(TF_EINVAL, "a head of several basis fields needs its weights");
     TF_HIP(hipSetDevice(f->dev));
     return TF_OK;
 }
@@ -1064,6 +1152,7 @@ extern "C" {
 
 tf_status tf_fno_set_params(tf_fno* f, const float* src, int32_t src_on_device) {
     if (!f || !src) return fail(TF_EINVAL, "NULL argument");
+    const int64_t NPARAMS = f->np;
     TF_HIP(hipSetDevice(f->dev));
     TF_HIP(hipMemcpyAsync(f->prm, src, NPARAMS * sizeof(float),
                           src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, f->st));
@@ -1079,6 +1168,7 @@ tf_status tf_fno_set_params(tf_fno* f, const float* src, int32_t src_on_device) 
 
 tf_status tf_fno_get_params(tf_fno* f, float* dst, int32_t dst_on_device) {
     if (!f || !dst) return fail(TF_EINVAL, "NULL argument");
+    const int64_t NPARAMS = f->np;
     TF_HIP(hipSetDevice(f->dev));
     TF_HIP(hipMemcpyAsync(dst, f->prm, NPARAMS * sizeof(float),
                           dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, f->st));
@@ -1086,17 +1176,17 @@ tf_status tf_fno_get_params(tf_fno* f, float* dst, int32_t dst_on_device) {
     return TF_OK;
 }
 
-tf_status tf_fno_forward(tf_fno* f, const float* params, int32_t batch, float* out) {
-    TRY(check_batch(f, batch));
+tf_status tf_fno_forward(tf_fno* f, const float* params, const float* head_w, int32_t batch, float* out) {
+    TRY(check_batch(f, batch, head_w));
     if (!params || !out) return fail(TF_EINVAL, "NULL argument");
-    return forward(f, params, batch, out);
+    return forward(f, params, head_w, batch, out);
 }
 
-tf_status tf_fno_infer(tf_fno* f, const float* params, int32_t batch, float* out) {
-    TRY(check_batch(f, batch));
+tf_status tf_fno_infer(tf_fno* f, const float* params, const float* head_w, int32_t batch, float* out) {
+    TRY(check_batch(f, batch, head_w));
     if (!params || !out) return fail(TF_EINVAL, "NULL argument");
     TRY(refresh_working(f));
-    if (!f->exec || f->g_params != params || f->g_out != out || f->g_batch != batch) {
+    if (!f->exec || f->g_params != params || f->g_w != head_w || f->g_out != out || f->g_batch != batch) {
         if (f->exec) {
             TF_HIP(hipStreamSynchronize(f->st));
             TF_HIP(hipGraphExecDestroy(f->exec));
@@ -1105,7 +1195,7 @@ tf_status tf_fno_infer(tf_fno* f, const float* params, int32_t batch, float* out
         hipGraph_t graph = nullptr;
         TF_HIP(hipStreamBeginCapture(f->cap, hipStreamCaptureModeThreadLocal));
         f->cur = f->cap;
-        const tf_status st = forward_body(f, params, batch, out);
+        const tf_status st = forward_body(f, params, head_w, batch, out);
         f->cur = f->st;
         const hipError_t e = hipStreamEndCapture(f->cap, &graph);
         if (st != TF_OK || e != hipSuccess) {
@@ -1119,6 +1209,7 @@ tf_status tf_fno_infer(tf_fno* f, const float* params, int32_t batch, float* out
             return fail(TF_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e2));
         }
         f->g_params = params;
+        f->g_w = head_w;
         f->g_out = out;
         f->g_batch = batch;
     }
@@ -1126,23 +1217,25 @@ tf_status tf_fno_infer(tf_fno* f, const float* params, int32_t batch, float* out
     return TF_OK;
 }
 
-tf_status tf_fno_loss_grad(tf_fno* f, const float* params, const float* target, int32_t batch, double* loss,
-                           float* grad) {
-    TRY(check_batch(f, batch));
+tf_status tf_fno_loss_grad(tf_fno* f, const float* params, const float* head_w, const float* target, int32_t batch,
+                           double* loss, float* grad) {
+    TRY(check_batch(f, batch, head_w));
     if (!f->training) return fail(TF_ESTATE, "surrogate was created for inference only");
     if (!params || !target) return fail(TF_EINVAL, "NULL argument");
-    TRY(forward(f, params, batch, f->out));
-    TRY(backward(f, params, target, batch));
+    const int64_t NPARAMS = f->np;
+    TRY(forward(f, params, head_w, batch, f->out));
+    TRY(backward(f, params, head_w, target, batch));
     if (grad) TF_HIP(hipMemcpyAsync(grad, f->grad, NPARAMS * sizeof(float), hipMemcpyDeviceToHost, f->st));
     if (loss) TF_HIP(hipMemcpyAsync(loss, f->dres, sizeof(double), hipMemcpyDeviceToHost, f->st));
     if (grad || loss) TF_HIP(hipStreamSynchronize(f->st));
     return TF_OK;
 }
 
-tf_status tf_fno_train_step(tf_fno* f, const float* params, const float* target, int32_t batch, double lr,
-                            double* loss) {
+tf_status tf_fno_train_step(tf_fno* f, const float* params, const float* head_w, const float* target,
+                            int32_t batch, double lr, double* loss) {
     if (!(lr >= 0.0) || !std::isfinite(lr)) return fail(TF_EINVAL, "lr must be finite and >= 0");
-    TRY(tf_fno_loss_grad(f, params, target, batch, nullptr, nullptr));
+    TRY(tf_fno_loss_grad(f, params, head_w, target, batch, nullptr, nullptr));
+    const int64_t NPARAMS = f->np;
     f->adam_t += 1;
     const double b1 = 0.9, b2 = 0.999;
     const float bc1 = float(1.0 - std::pow(b1, double(f->adam_t))), bc2 = float(1.0 - std::pow(b2, double(f->adam_t)));
@@ -1158,7 +1251,7 @@ tf_status tf_fno_train_step(tf_fno* f, const float* params, const float* target,
 }
 
 tf_status tf_fno_spectral_forward(tf_fno* f, const float* v, int32_t batch, float* modes) {
-    TRY(check_batch(f, batch));
+    TRY(check_batch(f, batch, nullptr, false));
     if (!v || !modes) return fail(TF_EINVAL, "NULL argument");
     const int64_t nb = batch;
     TRY(run(f, g_xcontract(f->fx, v, f->T1, batch), 24 * N, nb * NODE_SZ, nb * X1_SZ));
@@ -1167,7 +1260,7 @@ tf_status tf_fno_spectral_forward(tf_fno* f, const float* v, int32_t batch, floa
 }
 
 tf_status tf_fno_spectral_inverse(tf_fno* f, const float* modes, int32_t batch, float* u) {
-    TRY(check_batch(f, batch));
+    TRY(check_batch(f, batch, nullptr, false));
     if (!modes || !u) return fail(TF_EINVAL, "NULL argument");
     const int64_t nb = batch;
     TRY(run(f, g_zexpand(f->gs, modes, f->T2, batch), 128 * 48, nb * X3_SZ, nb * X2_SZ));
@@ -1181,6 +1274,7 @@ tf_status tf_fno_spectral_inverse(tf_fno* f, const float* modes, int32_t batch, 
 // parameters and (when training) the two Adam moments.
 tf_status tf_fno_save(tf_fno* f, const char* path) {
     if (!f || !path) return fail(TF_EINVAL, "NULL argument");
+    const int64_t NPARAMS = f->np;
     TF_HIP(hipSetDevice(f->dev));
     std::vector<float> h(NPARAMS);
     FILE* fp = std::fopen(path, "wb");
@@ -1202,6 +1296,7 @@ tf_status tf_fno_save(tf_fno* f, const char* path) {
 
 tf_status tf_fno_load(tf_fno* f, const char* path) {
     if (!f || !path) return fail(TF_EINVAL, "NULL argument");
+    const int64_t NPARAMS = f->np;
     TF_HIP(hipSetDevice(f->dev));
     FILE* fp = std::fopen(path, "rb");
     if (!fp) return fail(TF_EINVAL, std::string("cannot open ") + path);

@@ -91,15 +91,17 @@ _SIGS = {
                  ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "tf_profile": ([_P, ctypes.c_int32], ctypes.c_int),
     "tf_profile_read": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
-    "tf_fno_param_count": ([], ctypes.c_int64),
-    "tf_fno_create": ([ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "tf_fno_param_count": ([ctypes.c_int32], ctypes.c_int64),
+    "tf_fno_phasor_weights": ([ctypes.POINTER(tf_pulse), ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
+                              ctypes.c_int),
+    "tf_fno_create": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "tf_fno_destroy": ([_P], ctypes.c_int),
     "tf_fno_set_params": ([_P, _P, ctypes.c_int32], ctypes.c_int),
     "tf_fno_get_params": ([_P, _P, ctypes.c_int32], ctypes.c_int),
-    "tf_fno_forward": ([_P, _P, ctypes.c_int32, _P], ctypes.c_int),
-    "tf_fno_infer": ([_P, _P, ctypes.c_int32, _P], ctypes.c_int),
-    "tf_fno_loss_grad": ([_P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
-    "tf_fno_train_step": ([_P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)],
+    "tf_fno_forward": ([_P, _P, _P, ctypes.c_int32, _P], ctypes.c_int),
+    "tf_fno_infer": ([_P, _P, _P, ctypes.c_int32, _P], ctypes.c_int),
+    "tf_fno_loss_grad": ([_P, _P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
+    "tf_fno_train_step": ([_P, _P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)],
                           ctypes.c_int),
     "tf_fno_spectral_forward": ([_P, _P, ctypes.c_int32, _P], ctypes.c_int),
     "tf_fno_spectral_inverse": ([_P, _P, ctypes.c_int32, _P], ctypes.c_int),
@@ -462,22 +464,23 @@ FNO_N, FNO_WIDTH, FNO_MODES, FNO_NPARAM, FNO_HIDDEN, FNO_NOUT, FNO_LAYERS = 64, 
 FNO_NMODES = 4 * FNO_MODES ** 3
 
 
-def fno_param_shapes():
-    """(name, shape) of the flat parameter vector in order; R entries are
-    complex (stored as re, im pairs)."""
+def fno_param_shapes(nbasis=1):
+    """(name, shape) of the flat parameter vector in order for a head of
+    nbasis basis fields; R entries are complex (stored as re, im pairs)."""
     C, H = FNO_WIDTH, FNO_HIDDEN
     out = [("W0", (FNO_NPARAM + 3, C)), ("b0", (C,))]
     for l in range(1, FNO_LAYERS + 1):
         out += [(f"W{l}", (C, C)), (f"b{l}", (C,)), (f"R{l}", (FNO_NMODES, C, C))]
-    out += [("P1", (C, H)), ("c1", (H,)), ("P2", (H, FNO_NOUT)), ("c2", (FNO_NOUT,))]
+    out += [("P1", (C, H)), ("c1", (H,)), ("P2", (H, FNO_NOUT * nbasis)), ("c2", (FNO_NOUT * nbasis,))]
     return out
 
 
 def fno_flatten(params):
     """dict of numpy arrays (R complex) -> flat float32 vector."""
     import numpy as np
+    nbasis = np.shape(params["P2"])[1] // FNO_NOUT
     parts = []
-    for name, shape in fno_param_shapes():
+    for name, shape in fno_param_shapes(nbasis):
         a = np.asarray(params[name])
         if a.shape != shape:
             raise ValueError(f"{name} must have shape {shape}")
@@ -485,7 +488,7 @@ def fno_flatten(params):
             a = np.stack([a.real, a.imag], axis=-1)
         parts.append(np.ascontiguousarray(a, dtype=np.float32).ravel())
     flat = np.concatenate(parts)
-    assert flat.size == load().tf_fno_param_count()
+    assert flat.size == load().tf_fno_param_count(nbasis)
     return flat
 
 
@@ -493,8 +496,11 @@ def fno_unflatten(flat):
     """flat vector -> dict of float64 arrays (R complex128)."""
     import numpy as np
     flat = np.asarray(flat, dtype=np.float64)
+    nbasis = [k for k in (1, 2, 4) if load().tf_fno_param_count(k) == flat.size]
+    if not nbasis:
+        raise ValueError("not a surrogate parameter vector")
     out, o = {}, 0
-    for name, shape in fno_param_shapes():
+    for name, shape in fno_param_shapes(nbasis[0]):
         n = int(np.prod(shape)) * (2 if name.startswith("R") else 1)
         a = flat[o:o + n]
         o += n
@@ -502,17 +508,28 @@ def fno_unflatten(flat):
     return out
 
 
+def tf_fno_phasor_weights(pulse, nbasis):
+    """Head weights of a pulse (numpy float64 array of nbasis entries)."""
+    import numpy as np
+    w = (ctypes.c_double * 4)()
+    _check(load().tf_fno_phasor_weights(ctypes.byref(pulse_struct(pulse)), int(nbasis), w))
+    return np.array(w[:nbasis])
+
+
 class Surrogate:
     """Owning wrapper of a tf_fno (Fourier neural operator surrogate).
-    params, targets and outputs are contiguous float32 CUDA tensors."""
+    params, head weights, targets and outputs are contiguous float32 CUDA
+    tensors."""
 
-    def __init__(self, max_batch, training=False, stream=None):
+    def __init__(self, max_batch, training=False, nbasis=1, stream=None):
         h = ctypes.c_void_p()
-        _check(load().tf_fno_create(int(max_batch), 1 if training else 0, _stream_ptr(stream), ctypes.byref(h)))
+        _check(load().tf_fno_create(int(max_batch), 1 if training else 0, int(nbasis), _stream_ptr(stream),
+                                    ctypes.byref(h)))
         self.h = h
         self.max_batch = int(max_batch)
         self.training = bool(training)
-        self.nparams = int(load().tf_fno_param_count())
+        self.nbasis = int(nbasis)
+        self.nparams = int(load().tf_fno_param_count(self.nbasis))
 
     def close(self):
         if self.h is not None and self.h.value:
@@ -555,32 +572,41 @@ class Surrogate:
         _check(load().tf_fno_get_params(self.h, flat.ctypes.data, 0))
         return flat
 
-    def forward(self, p, out, graph=False):
-        """out <- surrogate(p); graph=True replays a captured hipGraph."""
+    def _w(self, w, B):
+        if w is None:
+            if self.nbasis != 1:
+                raise ValueError("this head needs per-sample weights")
+            return None
+        return self._dev(w, (B, self.nbasis), "head weights")
+
+    def forward(self, p, out, w=None, graph=False):
+        """out <- surrogate(p) with head weights w; graph=True replays a
+        captured hipGraph."""
         B = p.shape[0]
         pp = self._dev(p, (B, FNO_NPARAM), "params")
         po = self._dev(out, (B, FNO_NOUT, FNO_N, FNO_N, FNO_N), "out")
         fn = load().tf_fno_infer if graph else load().tf_fno_forward
-        _check(fn(self.h, pp, B, po))
+        _check(fn(self.h, pp, self._w(w, B), B, po))
         return out
 
-    def loss_grad(self, p, target, want_grad=True):
+    def loss_grad(self, p, target, w=None, want_grad=True):
         import numpy as np
         B = p.shape[0]
         pp = self._dev(p, (B, FNO_NPARAM), "params")
         pt = self._dev(target, (B, FNO_NOUT, FNO_N, FNO_N, FNO_N), "target")
         loss = ctypes.c_double()
         g = np.empty(self.nparams, np.float32) if want_grad else None
-        _check(load().tf_fno_loss_grad(self.h, pp, pt, B, ctypes.byref(loss),
+        _check(load().tf_fno_loss_grad(self.h, pp, self._w(w, B), pt, B, ctypes.byref(loss),
                                         g.ctypes.data if want_grad else None))
         return loss.value, g
 
-    def train_step(self, p, target, lr, want_loss=True):
+    def train_step(self, p, target, lr, w=None, want_loss=True):
         B = p.shape[0]
         pp = self._dev(p, (B, FNO_NPARAM), "params")
         pt = self._dev(target, (B, FNO_NOUT, FNO_N, FNO_N, FNO_N), "target")
         loss = ctypes.c_double()
-        _check(load().tf_fno_train_step(self.h, pp, pt, B, float(lr), ctypes.byref(loss) if want_loss else None))
+        _check(load().tf_fno_train_step(self.h, pp, self._w(w, B), pt, B, float(lr),
+                                         ctypes.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
 
     def spectral_forward(self, v, modes):

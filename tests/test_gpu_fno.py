@@ -37,18 +37,18 @@ def bf16_round(x):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def make_params(seed, r_scale=16.0):
+def make_params(seed, r_scale=16.0, hp=HP):
     """Oracle initialisation with the spectral weights scaled up so the
     Fourier branch carries a sizeable part of every layer, and non-zero
     biases; MFMA weights rounded to bf16."""
-    P = fno.init_params(seed, HP)
+    P = fno.init_params(seed, hp)
     rng = np.random.default_rng(seed + 1)
     for l in range(1, HP.layers + 1):
         P[f"R{l}"] = P[f"R{l}"] * r_scale
         P[f"b{l}"] = rng.normal(0, 0.1, HP.width)
     P["b0"] = rng.normal(0, 0.1, HP.width)
     P["c1"] = rng.normal(0, 0.1, HP.hidden)
-    P["c2"] = rng.normal(0, 0.1, HP.nout)
+    P["c2"] = rng.normal(0, 0.1, hp.nout * hp.nbasis)
     for k in list(P):
         if k.startswith(("W", "P")) and k != "W0":
             P[k] = bf16_round(P[k])
@@ -91,13 +91,15 @@ def test_truncated_transforms_match_oracle():
         assert rel(got_u, ref_u) <= SPECTRAL_TOL
 
 
-def run_forward(P, pb):
+def run_forward(P, pb, w=None):
     B = pb.shape[0]
-    with tf.Surrogate(B) as s:
+    nb = 1 if w is None else w.shape[1]
+    with tf.Surrogate(B, nbasis=nb) as s:
         s.set_params(P)
         pd = torch.from_numpy(pb.astype(np.float32)).cuda()
+        wd = None if w is None else torch.from_numpy(w.astype(np.float32)).cuda()
         out = torch.zeros((B, 6, 64, 64, 64), dtype=torch.float32, device="cuda")
-        s.forward(pd, out)
+        s.forward(pd, out, wd)
         return out.cpu().numpy().astype(np.float64)
 
 
@@ -127,15 +129,39 @@ def test_training_surrogate_forward_equals_inference_forward():
     assert np.array_equal(out.cpu().numpy().astype(np.float64), a)
 
 
-def test_gradient_matches_oracle():
-    P = make_params(7)
+def head_weights(rng, B, nb):
+    """Phasor-head weights of random pulses, rounded to float32 (the GPU input)."""
+    from synthetic import configs
+    rows = configs.c5_params(B, seed=int(rng.integers(1 << 30)))
+    w = np.array([tf.tf_fno_phasor_weights(configs.c5_pulse(r), nb) for r in rows])
+    return w.astype(np.float32).astype(np.float64)
+
+
+def test_four_basis_head_forward_matches_oracle():
+    hp4 = fno.HP(nbasis=4)
+    P = make_params(21, hp=hp4)
+    rng = np.random.default_rng(22)
+    pb = rng.uniform(size=(2, 8)).astype(np.float32).astype(np.float64)
+    w = head_weights(rng, 2, 4)
+    got = run_forward(P, pb, w)
+    ref = fno.forward(P, pb, hp4, w=w)
+    for b in range(2):
+        assert rel(got[b], ref[b]) <= FORWARD_TOL, b
+
+
+@pytest.mark.parametrize("nbasis", [1, 4])
+def test_gradient_matches_oracle(nbasis):
+    hp = fno.HP(nbasis=nbasis)
+    P = make_params(7, hp=hp)
     rng = np.random.default_rng(8)
     pb = rng.uniform(size=(2, 8)).astype(np.float32).astype(np.float64)
-    y = (fno.forward(P, pb, HP) + 0.5 * rng.standard_normal((2, 6, 64, 64, 64))).astype(np.float32)
-    L_ref, G_ref = fno.loss_and_grad(P, pb, y.astype(np.float64), HP)
-    with tf.Surrogate(2, training=True) as s:
+    w = head_weights(rng, 2, nbasis) if nbasis > 1 else None
+    y = (fno.forward(P, pb, hp, w=w) + 0.5 * rng.standard_normal((2, 6, 64, 64, 64))).astype(np.float32)
+    L_ref, G_ref = fno.loss_and_grad(P, pb, y.astype(np.float64), hp, w=w)
+    with tf.Surrogate(2, training=True, nbasis=nbasis) as s:
         s.set_params(P)
-        L, g = s.loss_grad(torch.from_numpy(pb.astype(np.float32)).cuda(), torch.from_numpy(y).cuda())
+        wd = None if w is None else torch.from_numpy(w.astype(np.float32)).cuda()
+        L, g = s.loss_grad(torch.from_numpy(pb.astype(np.float32)).cuda(), torch.from_numpy(y).cuda(), wd)
     G = tf.fno_unflatten(g)
     assert L == pytest.approx(L_ref, rel=FORWARD_TOL)
     for k, ref in G_ref.items():

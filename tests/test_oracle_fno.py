@@ -8,12 +8,13 @@ import pytest
 from oracle import fno
 
 
-def tiny():
-    return fno.HP(n=8, width=4, modes=2, nparam=8, hidden=6, nout=6, layers=3)
+def tiny(nbasis=1):
+    return fno.HP(n=8, width=4, modes=2, nparam=8, hidden=6, nout=6, layers=3, nbasis=nbasis)
 
 
-def test_gradients_match_central_differences():
-    hp = tiny()
+@pytest.mark.parametrize("nbasis", [1, 4])
+def test_gradients_match_central_differences(nbasis):
+    hp = tiny(nbasis)
     P = fno.init_params(1, hp)
     for k in list(P):
         if k.startswith("b") or k.startswith("c"):
@@ -21,7 +22,8 @@ def test_gradients_match_central_differences():
     rng = np.random.default_rng(2)
     pb = rng.uniform(size=(2, 8))
     y = rng.normal(size=(2, 6, 8, 8, 8))
-    L, G = fno.loss_and_grad(P, pb, y, hp)
+    w = rng.normal(size=(2, nbasis)) if nbasis > 1 else None
+    L, G = fno.loss_and_grad(P, pb, y, hp, w=w)
     h = 1e-6
     for k, v in P.items():
         flat = v.reshape(-1)
@@ -30,9 +32,9 @@ def test_gradients_match_central_differences():
             for part in ((1.0,) if not np.iscomplexobj(v) else (1.0, 1j)):
                 orig = flat[idx]
                 flat[idx] = orig + h * part
-                Lp = fno.loss(fno.forward(P, pb, hp), y)
+                Lp = fno.loss(fno.forward(P, pb, hp, w=w), y)
                 flat[idx] = orig - h * part
-                Lm = fno.loss(fno.forward(P, pb, hp), y)
+                Lm = fno.loss(fno.forward(P, pb, hp, w=w), y)
                 flat[idx] = orig
                 fd = (Lp - Lm) / (2 * h)
                 an = g[idx].real if part == 1.0 else g[idx].imag
@@ -63,3 +65,12 @@ def test_spectral_branch_is_translation_equivariant():
     f = lambda w: fno.spectral_inverse(np.einsum("bcq,qco->boq", fno.spectral_forward(w, hp), P["R1"]), hp)
     sh = lambda w: np.roll(w, (2, -3, 5), axis=(2, 3, 4))
     assert np.abs(f(sh(v)) - sh(f(v))).max() < 1e-12
+
+
+def test_phasor_head_is_the_plain_head_when_the_weights_select_one_group():
+    hp4 = tiny(4)
+    P = fno.init_params(6, hp4)
+    pb = np.random.default_rng(7).uniform(size=(1, 8))
+    o = fno.forward(P, pb, hp4, w=np.array([[0.0, 0.0, 1.0, 0.0]]))
+    P1 = dict(P, P2=P["P2"][:, 12:18], c2=P["c2"][12:18])
+    assert np.array_equal(o, fno.forward(P1, pb, tiny(1)))

@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1, help="untimed runs")
     ap.add_argument("--psatd-steps", type=int, default=None, help="override steps per run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "surrogate"])
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate timing on c3/c2")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -82,6 +83,66 @@ def cpu_baseline(n, seed=3):
     return {"value": n ** 3 / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"one float64 oracle step (scipy rfftn -> Eqs. (3)-(4) -> irfftn, "
                       f"{cores} workers) of a {n}^3 six-component state: {dt:.2f} s"}
+
+
+# surrogate training report whose held-out error the bench quotes (written by
+# python -m paper_2010_00409_amd.surrogate on MI355X; the weights themselves
+# are not kept, and inference time does not depend on their values)
+SURROGATE_REPORTS = ("surrogate_k4_head_4000x140.json", "surrogate_k4_head_4000x60.json")
+
+
+def surrogate_inference_bytes(batch):
+    """Algorithmic HBM bytes of one fused inference pass over `batch`
+    windows: every tensor the pass writes once and reads once, plus the
+    bf16 spectral weights once per pass."""
+    N, C, LINE = 64, 32, 12 * 32
+    x1, x2, x3 = N * N * 2 * LINE, 24 * N * 2 * LINE, 24 * 2 * 24 * LINE
+    node, out = N ** 3 * C, 6 * N ** 3
+    per_layer = 2 * x1 + 4 * x2 + 4 * x3    # y, z contractions, mixing, z, y expansions
+    lines = [x1 + node + x1,            # layer 0: U1 in, v1 out, X1 out (v0 recomputed)
+             x1 + node + node + x1,     # layer 1
+             x1 + node + out]           # layer 2 + projection
+    per_window = 4 * (x1 + 3 * per_layer + sum(lines))
+    weights = 3 * 6912 * 64 * 64 * 2
+    return per_window * batch + weights
+
+
+def surrogate_section(reps=20, batch=64):
+    """Time-to-focal-field of the surrogate (one graph replay per batch) and
+    of the solver (one exact jump step per window), measured live."""
+    import torch
+    from paper_2010_00409_amd import surrogate as sg
+    from paper_2010_00409_amd import tfocus as tf
+    from synthetic import configs
+
+    sur = tf.Surrogate(batch, nbasis=4)
+    sur.set_params(sg.init_params(0, 4))
+    t_b = sg.time_surrogate(sur, batch, reps=reps)
+    t_1 = sg.time_surrogate(sur, 1, reps=reps)
+    sur.close()
+    pulse = configs.c5_pulse(configs.c5_params(1, seed=configs.ROOT_SEED)[0])
+    t_sol1, t_solb = sg.time_solver(pulse, reps=3, batch=batch)
+    alg = surrogate_inference_bytes(batch)
+    achieved = alg / (t_b * batch) / 1e9
+    rep, src = None, None
+    for name in SURROGATE_REPORTS:
+        path = os.path.join(HERE, "profiles", name)
+        if os.path.exists(path):
+            rep, src = json.load(open(path)), "profiles/" + name
+            break
+    err = rep["test_rel_l2"] if rep else None
+    return {
+        "s_per_window": {"batch1": t_1, f"batch{batch}": t_b},
+        "solver_s_per_window": {"single": t_sol1, f"batch{batch}": t_solb},
+        "speedup": {"batch1_vs_single": t_sol1 / t_1, f"batch{batch}": t_solb / t_b},
+        "heldout_rel_l2": err, "heldout_source": src,
+        "meets_1e-2": (err["mean"] <= 1e-2) if err else None,
+        "roofline": {"bound": "hbm", "kernel": "fused inference pass", "achieved": achieved,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "alg_bytes_per_launch": alg},
+        "workload": ("C5: 3-layer FNO (width 32, 12 modes/axis, four-basis head) -> 6 x 64^3 focal window; "
+                     "solver: 96x256x256 layer, dx = lambda/12, one exact step to t = R0, cut-out"),
+    }
 
 
 def bench_c4(args):
@@ -136,6 +197,16 @@ def main():
         sys.exit(2)
     if args.workload == "c4":
         bench_c4(args)
+        return
+    if args.workload == "surrogate":
+        sec = surrogate_section(reps=max(args.steps, 1))
+        t = sec["s_per_window"]["batch64"]
+        print(json.dumps({
+            "metric": "surrogate focal windows/s (one graph replay per 64 windows)",
+            "value": 1.0 / t, "unit": "windows/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": t * 64 * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16", "data": "synthetic", "config": {"workload": sec["workload"]},
+            "roofline": sec["roofline"], "surrogate": sec}), flush=True)
         return
     import torch
     from paper_2010_00409_amd import tfocus as tf
@@ -228,6 +299,8 @@ def main():
                      "traffic": traffic, "alg_bytes_per_launch": alg_bytes},
         "focal_peak_abs": peak_field,
     }
+    if not args.no_surrogate:
+        line["surrogate"] = surrogate_section()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n[0])
     print(json.dumps(line), flush=True)

@@ -48,6 +48,7 @@ constexpr int64_t X2_SZ = int64_t(KS) * N * 2 * LINE;       // 1,179,648
 constexpr int64_t X3_SZ = int64_t(KS) * 2 * KS * LINE;      // 442,368
 constexpr int64_t OUT_SZ = int64_t(NOUT) * N3;
 constexpr int CHUNK = 4096;               // nodes per split-K block of the weight gradients
+constexpr int KSLOTS = 4 * 2 * 2 * 32 * 8; // one 128-row operand in kappa fragment order
 constexpr int NCHUNK = N3 / CHUNK;
 
 // Flat parameter vector (fp32): W0 (11x32), b0, then per layer W (32x32),
@@ -74,9 +75,23 @@ __device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// erf by Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7): for u >= 0,
+// erf(u) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-u^2), t = 1 / (1 + p u).
+// ex = exp(-u^2) is passed in, so GELU' reuses it for the Gaussian.
+__device__ __forceinline__ float erf_as(float u, float ex) {
+    const float a = fabsf(u);
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * a);
+    const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+    const float r = 1.0f - poly * ex;
+    return u < 0.0f ? -r : r;
+}
+__device__ __forceinline__ float gelu(float x) {
+    const float ex = __expf(-0.5f * x * x);
+    return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f, ex));
+}
 __device__ __forceinline__ float gelu_d(float x) {
-    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+    const float ex = __expf(-0.5f * x * x);
+    return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f, ex)) + x * ex * 0.39894228040143268f;
 }
 
 __device__ __forceinline__ float ldf(const float* p) { return *p; }
@@ -100,6 +115,7 @@ struct Operand {
     Ix r, c;              // row and column maps
     int ones_from;        // rows >= ones_from read 1 (A only; large value: none)
     int fast_k;           // consecutive threads walk k (k is the contiguous index)
+    int vec;              // groups of 4 along the contiguous index are contiguous and aligned
 };
 struct Result {
     float* p;
@@ -113,6 +129,65 @@ struct GemmArgs {
     Result c;
     int M, N, K;
 };
+
+__device__ __forceinline__ void ld4(const float* p, float v[4]) {
+    const float4 q = *(const float4*)p;
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+}
+__device__ __forceinline__ void ld4(const bf16* p, float v[4]) {
+    const uint2 q = *(const uint2*)p;           // element 0 in the low half
+    v[0] = __uint_as_float(q.x << 16); v[1] = __uint_as_float(q.x & 0xffff0000u);
+    v[2] = __uint_as_float(q.y << 16); v[3] = __uint_as_float(q.y & 0xffff0000u);
+}
+
+// Stage a ROWS x 32 slice of an operand in LDS as bf16 (hi and, for SPLIT,
+// lo parts), k contiguous.  "Rows" are the M index of A or the N index of B.
+template <int ROWS, int NT, typename TT, bool SPLIT, bool IS_B>
+__device__ __forceinline__ void stage(bf16* s0, bf16* s1, const TT* P, const Operand& o, int r0, int k0, int nrows,
+                                      int K) {
+    constexpr int BK = 32, PITCH = BK + 8;
+    const int tid = threadIdx.x;
+    auto put = [&](int rr, int kk, float v) {
+        const bf16 hi = (bf16)v;
+        s0[rr * PITCH + kk] = hi;
+        if constexpr (SPLIT) s1[rr * PITCH + kk] = (bf16)(v - (float)hi);
+    };
+    auto off = [&](int gr, int gk) -> int64_t {
+        return IS_B ? ixoff(o.r, gk) + ixoff(o.c, gr) : ixoff(o.r, gr) + ixoff(o.c, gk);
+    };
+    auto one = [&](int gr) { return !P || (!IS_B && gr >= o.ones_from); };
+    if (o.vec) {
+        if (o.fast_k) {
+            for (int e = tid; e < ROWS * BK / 4; e += NT) {
+                const int rr = e / (BK / 4), kk = 4 * (e % (BK / 4));
+                const int gr = r0 + rr, gk = k0 + kk;
+                float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                if (gr < nrows && gk < K) ld4(P + off(gr, gk), v);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) put(rr, kk + q, v[q]);
+            }
+        } else {
+            for (int e = tid; e < ROWS * BK / 4; e += NT) {
+                const int rr = 4 * (e % (ROWS / 4)), kk = e / (ROWS / 4);
+                const int gr = r0 + rr, gk = k0 + kk;
+                float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                if (gr < nrows && gk < K) ld4(P + off(gr, gk), v);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) put(rr + q, kk, v[q]);
+            }
+        }
+        return;
+    }
+    for (int e = tid; e < ROWS * BK; e += NT) {
+        int rr, kk;
+        if (o.fast_k) { rr = e / BK; kk = e % BK; }
+        else          { rr = e % ROWS; kk = e / ROWS; }
+        const int gr = r0 + rr, gk = k0 + kk;
+        float v = 0.0f;
+        if (gr < nrows && gk < K) v = one(gr) ? 1.0f : ldf(P + off(gr, gk));
+        put(rr, kk, v);
+    }
+}
 
 // Each wave owns 32x32 output sub-tiles; the K loop stages 32-wide slices of
 // A and B in LDS as bf16 (hi and, for SPLIT, lo parts), k contiguous so each
@@ -140,30 +215,9 @@ __global__ __launch_bounds__(64 * NW) void k_gemm(GemmArgs g) {
         for (int r = 0; r < 16; ++r) acc[p][r] = 0.0f;
 
     for (int k0 = 0; k0 < g.K; k0 += BK) {
-        for (int e = threadIdx.x; e < BM * BK; e += NT) {
-            int i, k;
-            if (g.a.fast_k) { i = e / BK; k = e % BK; }
-            else            { i = e % BM; k = e / BM; }
-            const int gi = m0 + i, gk = k0 + k;
-            float v = 0.0f;
-            if (gi < g.M && gk < g.K)
-                v = (!A || gi >= g.a.ones_from) ? 1.0f : ldf(A + ixoff(g.a.r, gi) + ixoff(g.a.c, gk));
-            const bf16 hi = (bf16)v;
-            sa[0][i * PITCH + k] = hi;
-            if constexpr (SPLIT) sa[NP - 1][i * PITCH + k] = (bf16)(v - (float)hi);
-        }
-        for (int e = threadIdx.x; e < BN * BK; e += NT) {
-            int j, k;
-            if (g.b.fast_k) { j = e / BK; k = e % BK; }
-            else            { j = e % BN; k = e / BN; }
-            const int gj = n0 + j, gk = k0 + k;
-            float v = 0.0f;
-            if (gj < g.N && gk < g.K) v = B ? ldf(B + ixoff(g.b.r, gk) + ixoff(g.b.c, gj)) : 1.0f;
-            const bf16 hi = (bf16)v;
-            sb[0][j * PITCH + k] = hi;
-            if constexpr (SPLIT) sb[NP - 1][j * PITCH + k] = (bf16)(v - (float)hi);
-        }
-        __syncthreads();
+        stage<BM, NT, TA, SPLIT, false>(sa[0], sa[NP - 1], A, g.a, m0, k0, g.M, g.K);
+        stage<BN, NT, TB, SPLIT, true>(sb[0], sb[NP - 1], B, g.b, n0, k0, g.N, g.K);
+    __syncthreads();
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
             const int st = wave * PER + p, mt = st / SUBN, nt = st % SUBN;
@@ -456,19 +510,304 @@ __global__ __launch_bounds__(256) void k_proj(ProjArgs a) {
 
 __device__ __forceinline__ float coord(int i) { return float(i - N / 2) / float(N / 2); }
 
-// v0[b][node][c] = b0[c] + sum_i p[b][i] W0[i][c] + x W0[8][c] + y W0[9][c] + z W0[10][c]
+// v0[b][node][c] = b0[c] + sum_i p[b][i] W0[i][c] + x W0[8][c] + y W0[9][c] + z W0[10][c],
+// always summed in this order
+__device__ __forceinline__ float lift_base(const float* pb, const float* w0, const float* b0, int c) {
+    float s = b0[c];
+    for (int i = 0; i < NPAR; ++i) s += pb[i] * w0[i * C + c];
+    return s;
+}
+__device__ __forceinline__ float lift_at(float base, const float* w0, int c, int x, int y, int z) {
+    float s = base;
+    s += coord(x) * w0[8 * C + c];
+    s += coord(y) * w0[9 * C + c];
+    s += coord(z) * w0[10 * C + c];
+    return s;
+}
+
 __global__ void k_lift(const float* p, const float* w0, const float* b0, float* v, int64_t total) {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= total) return;
     const int c = idx & (C - 1);
     const int64_t nb = idx >> 5;
     const int node = int(nb % N3), b = int(nb / N3);
-    float s = b0[c];
-    for (int i = 0; i < NPAR; ++i) s += p[b * NPAR + i] * w0[i * C + c];
-    s += coord(node % N) * w0[8 * C + c];
-    s += coord((node / N) % N) * w0[9 * C + c];
-    s += coord(node / (N * N)) * w0[10 * C + c];
-    v[idx] = s;
+    v[idx] = lift_at(lift_base(p + b * NPAR, w0, b0, c), w0, c, node % N, (node / N) % N, node / (N * N));
+}
+
+// ---------------------------------------------------------------------------
+// Fused inference kernels: no activation of the forward pass is kept, and
+// the first x contraction of every layer is taken from the registers of the
+// kernel that produced the layer's input.
+// ---------------------------------------------------------------------------
+
+// 8 (or 4) consecutive floats from a 16-byte aligned address, or zeros
+__device__ __forceinline__ void ld8(const float* p, bool in, float v[8]) {
+    if (in) {
+        const float4 q0 = *(const float4*)p, q1 = *(const float4*)(p + 4);
+        v[0] = q0.x; v[1] = q0.y; v[2] = q0.z; v[3] = q0.w; v[4] = q1.x; v[5] = q1.y; v[6] = q1.z; v[7] = q1.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = 0.0f;
+    }
+}
+__device__ __forceinline__ void ld4c(const float* p, bool in, float v[4]) {
+    if (in) {
+        const float4 q = *(const float4*)p;
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+        v[0] = v[1] = v[2] = v[3] = 0.0f;
+    }
+}
+
+// element e of (hi, lo) <- bf16 split of v
+__device__ __forceinline__ void split(float v, bf16x8& hi, bf16x8& lo, int e) {
+    const bf16 h = (bf16)v;
+    hi[e] = h;
+    lo[e] = (bf16)(v - (float)h);
+}
+
+struct InfArgs {
+    const float* gx;      // inverse x matrix [64][24]
+    const float* fx;      // forward x matrix [24][64]
+    const float* ln;      // spectral lines [lines][24][32] (U1); overwritten by the next layer's X1
+    const float* act;     // v_l [lines][64][32], or nullptr: v_0 recomputed from the lift
+    const float* p;       // [B][8] parameters (lift)
+    const float* w0;
+    const float* b0;
+    const bf16* w;        // W_l [32][32]
+    const float* bias;    // b_l
+    float* vout;          // v_{l+1} (not the last layer)
+    float* x1out;         // X1 of layer l+1, written over the line's U1
+    // projection (last layer), operands in kappa fragment order
+    const bf16* p1k;      // [4][2][2][32][8]
+    const float* c1;
+    const bf16* p2k;      // [B][4][2][2][32][8]
+    const float* c2e;     // [B][6]
+    float* out;           // [B][6][N3]
+    int nlines;
+};
+
+// Lift and the first x contraction, one wave per x-line:
+//   X1[(s,kx)][c] = sum_x Fx[(s,kx)][x] v0[x][c]    (split bf16)
+__global__ __launch_bounds__(256) void k_lift_x(InfArgs a) {
+    const int lane = threadIdx.x & 63, t = lane & 31, grp = lane >> 5;
+    const int line = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (line >= a.nlines) return;
+    const int b = line / (N * N), zy = line % (N * N);
+    const float base = lift_base(a.p + b * NPAR, a.w0, a.b0, t);
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        bf16x8 ah, al, bh, bl;
+        float fr[8];
+        ld8(a.fx + t * N + 16 * ks + 8 * grp, t < 24, fr);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int x = 16 * ks + 8 * grp + e;
+            split(fr[e], ah, al, e);
+            split(lift_at(base, a.w0, t, x, zy % N, zy / N), bh, bl, e);
+        }
+        acc = mfma(ah, bh, acc);
+        acc = mfma(ah, bl, acc);
+        acc = mfma(al, bh, acc);
+    }
+    float* o = a.x1out + int64_t(line) * 24 * C + t;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = 8 * (r >> 2) + 4 * grp + (r & 3);
+        if (i < 24) o[i * C] = acc[r];
+    }
+}
+
+// Inverse x transform + pointwise branch + GELU of a layer that is not the
+// last, then the next layer's x contraction from the registers:
+//   v[x][o]  = GELU(sum_k Gx[x][k] U1[k][o] + sum_c v_l[x][c] W[c][o] + b[o])
+//   X1[i][o] = sum_x Fx[i][x] v[x][o]
+// The accumulator of v holds row x = 32 h + kappa(s, g, e) in register 8 s + e
+// of lane (o, g), so it is the B operand of the contraction over x with the
+// constant Fx gathered in that order.
+__global__ __launch_bounds__(256) void k_line_fwd(InfArgs a) {
+    const int lane = threadIdx.x & 63, t = lane & 31, grp = lane >> 5;
+    const int line = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (line >= a.nlines) return;
+    const int b = line / (N * N), zy = line % (N * N);
+    bf16x8 cmh[2][2], cml[2][2], wf[2], lh[2], ll[2];
+    const float* ln = a.ln + int64_t(line) * 24 * C;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const bool in = 16 * s + 8 * grp < 24;
+        float g0[8], g1[8];
+        ld8(a.gx + t * 24 + 16 * s + 8 * grp, in, g0);
+        ld8(a.gx + (32 + t) * 24 + 16 * s + 8 * grp, in, g1);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 16 * s + 8 * grp + e;
+            wf[s][e] = a.w[k * C + t];
+            split(in ? ln[k * C + t] : 0.0f, lh[s], ll[s], e);
+            split(g0[e], cmh[0][s], cml[0][s], e);
+            split(g1[e], cmh[1][s], cml[1][s], e);
+        }
+    }
+    const int64_t base = int64_t(line) * N * C;
+    float lb[2][8];
+    if (!a.act) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) lb[s][e] = lift_base(a.p + b * NPAR, a.w0, a.b0, 16 * s + 8 * grp + e);
+    }
+    f32x16 acc[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[h][r] = 0.0f;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            acc[h] = mfma(cmh[h][s], lh[s], acc[h]);
+            acc[h] = mfma(cmh[h][s], ll[s], acc[h]);
+            acc[h] = mfma(cml[h][s], lh[s], acc[h]);
+        }
+        const int x = 32 * h + t;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            bf16x8 af;
+            if (a.act) {
+                const float* ap = a.act + base + x * C + 16 * s + 8 * grp;
+                const float4 u0 = *(const float4*)ap;
+                const float4 u1 = *(const float4*)(ap + 4);
+                af[0] = (bf16)u0.x; af[1] = (bf16)u0.y; af[2] = (bf16)u0.z; af[3] = (bf16)u0.w;
+                af[4] = (bf16)u1.x; af[5] = (bf16)u1.y; af[6] = (bf16)u1.z; af[7] = (bf16)u1.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    af[e] = (bf16)lift_at(lb[s][e], a.w0, 16 * s + 8 * grp + e, x, zy % N, zy / N);
+            }
+            acc[h] = mfma(af, wf[s], acc[h]);
+        }
+        const float bt = a.bias[t];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int xr = 32 * h + 8 * (r >> 2) + 4 * grp + (r & 3);
+            const float v = gelu(acc[h][r] + bt);
+            acc[h][r] = v;
+            a.vout[base + xr * C + t] = v;
+        }
+    }
+    f32x16 xacc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) xacc[r] = 0.0f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            bf16x8 ah, al, bh, bl;
+            // kappa(s, g, e) for e = 0..3 and 4..7 is two runs of 4 consecutive x
+            float fr[8];
+            ld4c(a.fx + t * N + 32 * h + 16 * s + 4 * grp, t < 24, fr);
+            ld4c(a.fx + t * N + 32 * h + 16 * s + 8 + 4 * grp, t < 24, fr + 4);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                split(fr[e], ah, al, e);
+                split(acc[h][8 * s + e], bh, bl, e);
+            }
+            xacc = mfma(ah, bh, xacc);
+            xacc = mfma(ah, bl, xacc);
+            xacc = mfma(al, bh, xacc);
+        }
+    float* o = a.x1out + int64_t(line) * 24 * C + t;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = 8 * (r >> 2) + 4 * grp + (r & 3);
+        if (i < 24) o[i * C] = xacc[r];
+    }
+}
+
+// Last layer fused with the projection.  The layer is computed transposed,
+// v^T[o][x] = sum_k U1^T[o][k] Gx^T[k][x] + sum_c W^T[o][c] v_l^T[c][x] + b[o],
+// so lane (x, g) holds channel o = kappa(s, g, e) in register 8 s + e: the B
+// operand of h^T = P1^T v^T over c, with P1 gathered in that order.  The
+// projection then runs as in k_proj.
+__global__ __launch_bounds__(256) void k_line_proj(InfArgs a) {
+    const int lane = threadIdx.x & 63, t = lane & 31, grp = lane >> 5;
+    const int line = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (line >= a.nlines) return;
+    const int b = line / (N * N), zy = line % (N * N);
+    bf16x8 wf[2], lh[2], ll[2];
+    const float* ln = a.ln + int64_t(line) * 24 * C;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 16 * s + 8 * grp + e;
+            wf[s][e] = a.w[k * C + t];
+            split(k < 24 ? ln[k * C + t] : 0.0f, lh[s], ll[s], e);
+        }
+    const bf16x8* p1k = (const bf16x8*)a.p1k + grp * 32 + t;          // + (mt * 2 + s) * 64
+    const bf16x8* p2k = (const bf16x8*)(a.p2k + int64_t(b) * KSLOTS) + grp * 32 + t;
+    const float* c2 = a.c2e + b * NOUT;
+    const int64_t base = int64_t(line) * N * C;
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+        const int x = 32 * h + t;
+        f32x16 acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            bf16x8 cmh, cml;
+            float gr[8];
+            ld8(a.gx + x * 24 + 16 * s + 8 * grp, 16 * s + 8 * grp < 24, gr);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) split(gr[e], cmh, cml, e);
+            acc = mfma(lh[s], cmh, acc);
+            acc = mfma(ll[s], cmh, acc);
+            acc = mfma(lh[s], cml, acc);
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const float* ap = a.act + base + x * C + 16 * s + 8 * grp;
+            const float4 u0 = *(const float4*)ap;
+            const float4 u1 = *(const float4*)(ap + 4);
+            bf16x8 af;
+            af[0] = (bf16)u0.x; af[1] = (bf16)u0.y; af[2] = (bf16)u0.z; af[3] = (bf16)u0.w;
+            af[4] = (bf16)u1.x; af[5] = (bf16)u1.y; af[6] = (bf16)u1.z; af[7] = (bf16)u1.w;
+            acc = mfma(wf[s], af, acc);
+        }
+        bf16x8 vf[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) vf[s][e] = (bf16)(acc[8 * s + e] + a.bias[kappa(s, grp, e)]);
+        f32x16 oacc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) oacc[r] = 0.0f;
+#pragma unroll 1
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x16 hacc;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) hacc[r] = 0.0f;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) hacc = mfma(p1k[(mt * 2 + s) * 64], vf[s], hacc);
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                bf16x8 hf;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int hd = 32 * mt + kappa(s, grp, e);
+                    hf[e] = (bf16)gelu(hacc[8 * s + e] + a.c1[hd]);
+                }
+                oacc = mfma(p2k[(mt * 2 + s) * 64], hf, oacc);
+            }
+        }
+        float* op = a.out + int64_t(b) * OUT_SZ + int64_t(zy) * N + x;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = 4 * grp + r;
+            if (o < NOUT) op[int64_t(o) * N3] = oacc[r] + c2[o];
+        }
+    }
 }
 
 // per (sample, z plane): sum_node g, and sum_node coord_d g, for every channel
@@ -597,7 +936,10 @@ __global__ void k_expand_r(const float* r, bf16* rb) {
 // Effective projection of sample b for a head of nb basis fields:
 //   P2eff[b][hd][c] = sum_k w[b][k] P2[hd][6k + c],  c2eff[b][c] = sum_k w[b][k] c2[6k + c]
 // (w = 1 when nb = 1 and no weights are given).
-__global__ void k_head_eff(const float* p2, const float* c2, const float* w, int nb, int B, bf16* p2e, float* c2e) {
+// and in the projection's kappa order, padded to 32 outputs:
+//   p2k[b][mt][s][g][t][e] = P2eff[b][32 mt + kappa(s, g, e)][t]  (0 for t >= 6)
+__global__ void k_head_eff(const float* p2, const float* c2, const float* w, int nb, int B, bf16* p2e, float* c2e,
+                           bf16* p2k) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int per = (HID + 1) * NOUT;
     if (i >= B * per) return;
@@ -605,8 +947,16 @@ __global__ void k_head_eff(const float* p2, const float* c2, const float* w, int
     const float* src = r < HID ? p2 + int64_t(r) * NOUT * nb : c2;
     float s = 0.0f;
     for (int k = 0; k < nb; ++k) s += (w ? w[b * nb + k] : 1.0f) * src[NOUT * k + c];
-    if (r < HID) p2e[(int64_t(b) * HID + r) * NOUT + c] = (bf16)s;
-    else c2e[b * NOUT + c] = s;
+    if (r < HID) {
+        p2e[(int64_t(b) * HID + r) * NOUT + c] = (bf16)s;
+        // r = 32 mt + kappa(s', g, e): invert kappa (16 s' + 8 (e >> 2) + 4 g + (e & 3))
+        const int mt = r >> 5, q = r & 31, sp = q >> 4, eh = (q >> 3) & 1, g = (q >> 2) & 1, el = q & 3;
+        const int e = 4 * eh + el;
+        bf16* d = p2k + int64_t(b) * KSLOTS;
+        d[((((mt * 2 + sp) * 2 + g) * 32 + c) * 8) + e] = (bf16)s;
+    } else {
+        c2e[b * NOUT + c] = s;
+    }
 }
 
 // dL/dP2 and dL/dc2 from the per-sample gradients of the effective head
@@ -619,6 +969,14 @@ __global__ void k_head_grad(const float* geff, const float* w, int nb, int B, fl
     float s = 0.0f;
     for (int b = 0; b < B; ++b) s += (w ? w[b * nb + k] : 1.0f) * geff[(int64_t(b) * (HID + 1) + r) * NOUT + c];
     g[int64_t(r) * cols + col] = s;
+}
+
+// P1 in the projection's kappa order: [mt][s][g][t][e] = P1[kappa(s, g, e)][32 mt + t]
+__global__ void k_p1_kappa(const float* p1, bf16* dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C * HID) return;
+    const int e = i & 7, t = (i >> 3) & 31, g = (i >> 8) & 1, s = (i >> 9) & 1, mt = i >> 10;
+    dst[i] = (bf16)p1[kappa(s, g, e) * HID + 32 * mt + t];
 }
 
 __global__ void k_to_bf16(const float* src, bf16* dst, int n) {
@@ -682,7 +1040,23 @@ inline bool fits(const Result& o, int rows, int cols, int by, int bz, int64_t si
 }
 
 inline Operand opnd(const void* p, Ix r, Ix c, int64_t b1, int64_t b2, int fast_k, int ones_from = 1 << 30) {
-    return Operand{p, b1, b2, r, c, ones_from, fast_k};
+    return Operand{p, b1, b2, r, c, ones_from, fast_k, 0};
+}
+
+// Whether groups of 4 along the operand's contiguous index are contiguous and
+// aligned for 4-element loads (rows x cols is the operand's shape).
+inline bool vec_ok(const Operand& o, int rows, int cols, bool is_b, size_t elem) {
+    if (!o.p || o.ones_from < (1 << 30)) return false;
+    const bool k_is_row = is_b;                 // A: (M, K); B: (K, N)
+    const Ix fast = o.fast_k ? (k_is_row ? o.r : o.c) : (k_is_row ? o.c : o.r);
+    const Ix slow = o.fast_k ? (k_is_row ? o.c : o.r) : (k_is_row ? o.r : o.c);
+    const int fext = o.fast_k ? (k_is_row ? rows : cols) : (k_is_row ? cols : rows);
+    auto mult4 = [](int64_t v) { return v % 4 == 0; };
+    if (fast.lo != 1 || fast.sh < 2 || fext % 4) return false;
+    if (fast.sh < 30 && !mult4(fast.hi)) return false;
+    if (!mult4(slow.lo) || (slow.sh < 30 && !mult4(slow.hi))) return false;
+    if (!mult4(o.b1) || !mult4(o.b2)) return false;
+    return (uintptr_t)o.p % (4 * elem) == 0;
 }
 inline Result res(float* p, Ix r, Ix c, int64_t b1, int64_t b2, float alpha = 1.0f, int acc = 0) {
     return Result{p, b1, b2, r, c, alpha, acc};
@@ -764,7 +1138,7 @@ struct tf_fno {
 
     std::vector<void*> allocs;
     float *prm = nullptr, *grad = nullptr, *am = nullptr, *av = nullptr;
-    bf16 *wb[LAYERS] = {}, *rb[LAYERS] = {}, *p1b = nullptr, *p2e = nullptr;
+    bf16 *wb[LAYERS] = {}, *rb[LAYERS] = {}, *p1b = nullptr, *p2e = nullptr, *p1k = nullptr, *p2k = nullptr;
     float *c2e = nullptr, *geff = nullptr;
     float *fx, *fxT, *gx, *gxT, *fs, *fsT, *gs, *gsT;
     float* V[4] = {};
@@ -812,10 +1186,12 @@ tf_status launched() {
     return TF_OK;
 }
 
-tf_status run(tf_fno* f, const Gemm& g, int64_t sa, int64_t sb, int64_t sc) {
+tf_status run(tf_fno* f, Gemm g, int64_t sa, int64_t sb, int64_t sc, size_t ea = 4, size_t eb = 4) {
     if (!fits(g.g.a, g.g.M, g.g.K, g.by, g.bz, sa) || !fits(g.g.b, g.g.K, g.g.N, g.by, g.bz, sb) ||
         !fits(g.g.c, g.g.M, g.g.N, g.by, g.bz, sc))
         return fail(TF_EINVAL, "internal: GEMM operand exceeds its buffer");
+    g.g.a.vec = vec_ok(g.g.a, g.g.M, g.g.K, false, ea);
+    g.g.b.vec = vec_ok(g.g.b, g.g.K, g.g.N, true, eb);
     g.fn(g.g, g.by, g.bz, f->cur);
     return launched();
 }
@@ -948,6 +1324,9 @@ tf_status tf_fno_create(int32_t max_batch, int32_t training, int32_t nbasis, voi
     TRY(f->alloc(&f->p1b, C * HID));
     TRY(f->alloc(&f->p2e, B * HID * NOUT));
     TRY(f->alloc(&f->c2e, B * NOUT));
+    TRY(f->alloc(&f->p1k, C * HID));
+    TRY(f->alloc(&f->p2k, B * KSLOTS));
+    TF_HIP(hipMemset(f->p2k, 0, B * KSLOTS * sizeof(bf16)));     // rows t >= 6 stay 0
 
     Tables t = build_tables();
     float* tab = nullptr;
@@ -1016,6 +1395,7 @@ tf_status refresh_working(tf_fno* f) {
         hipLaunchKernelGGL(k_expand_r, dim3((n + 255) / 256), dim3(256), 0, f->cur, f->prm + off_r(l), f->rb[l]);
     }
     hipLaunchKernelGGL(k_to_bf16, dim3((C * HID + 255) / 256), dim3(256), 0, f->cur, f->prm + OFF_P1, f->p1b, C * HID);
+    hipLaunchKernelGGL(k_p1_kappa, dim3((C * HID + 255) / 256), dim3(256), 0, f->cur, f->prm + OFF_P1, f->p1k);
     TRY(launched());
     f->working_stale = false;
     return TF_OK;
@@ -1023,13 +1403,16 @@ tf_status refresh_working(tf_fno* f) {
 
 // Forward pass.  Training keeps v_l, z_l and the modes of every layer for the
 // backward pass; inference ping-pongs two node tensors.
+tf_status forward_infer(tf_fno* f, const float* params, int B, float* out);
+
 tf_status forward_body(tf_fno* f, const float* params, const float* hw, int B, float* out) {
     const int64_t nb = B;
     {
         const int n = B * (HID + 1) * NOUT;
         hipLaunchKernelGGL(k_head_eff, dim3((n + 255) / 256), dim3(256), 0, f->cur, f->prm + OFF_P2,
-                           f->prm + off_c2(f->nb), hw, f->nb, B, f->p2e, f->c2e);
+                           f->prm + off_c2(f->nb), hw, f->nb, B, f->p2e, f->c2e, f->p2k);
     }
+    if (!f->training) return forward_infer(f, params, B, out);
     {
         const int64_t tot = nb * NODE_SZ;
         hipLaunchKernelGGL(k_lift, dim3((tot + 255) / 256), dim3(256), 0, f->cur, params, f->prm + OFF_W0,
@@ -1043,7 +1426,7 @@ tf_status forward_body(tf_fno* f, const float* params, const float* hw, int B, f
         TRY(run(f, g_xcontract(f->fx, v, f->T1, B), 24 * N, szN, sz1));
         TRY(run(f, g_ycontract(f->fs, f->T1, f->T2, B), 48 * 128, sz1, sz2));
         TRY(run(f, g_zcontract(f->fs, f->T2, modes, B), 48 * 128, sz2, sz3));
-        TRY(run(f, g_mix(modes, f->rb[l], f->Y, B, false), sz3, int64_t(NMODES) * 4096, sz3));
+        TRY(run(f, g_mix(modes, f->rb[l], f->Y, B, false), sz3, int64_t(NMODES) * 4096, sz3, 4, 2));
         TRY(run(f, g_zexpand(f->gs, f->Y, f->T2, B), 128 * 48, sz3, sz2));
         TRY(run(f, g_yexpand(f->gs, f->T2, f->T1, B), 128 * 48, sz2, sz1));
         float* nv = f->training ? f->V[l + 1] : (v == f->V[0] ? f->V[1] : f->V[0]);
@@ -1057,6 +1440,39 @@ tf_status forward_body(tf_fno* f, const float* params, const float* hw, int B, f
                B * (N3 / 32), 0};
     hipLaunchKernelGGL(k_proj, dim3((p.ntiles + 3) / 4), dim3(256), 0, f->cur, p);
     return launched();
+}
+
+// Inference: lift + first x contraction, then per layer the y and z
+// contractions, mixing and expansions, and one fused x-line kernel.
+tf_status forward_infer(tf_fno* f, const float* params, int B, float* out) {
+    const int64_t nb = B;
+    const int64_t sz1 = nb * X1_SZ, sz2 = nb * X2_SZ, sz3 = nb * X3_SZ;
+    const int lines = B * N * N;
+    InfArgs a{f->gx, f->fx, f->T1, nullptr, params, f->prm + OFF_W0, f->prm + OFF_B0, nullptr, nullptr,
+              nullptr, f->T1, f->p1k, f->prm + OFF_C1, f->p2k, f->c2e, out, lines};
+    hipLaunchKernelGGL(k_lift_x, dim3((lines + 3) / 4), dim3(256), 0, f->cur, a);
+    TRY(launched());
+    const float* v = nullptr;                 // v_0 is recomputed, never stored
+    for (int l = 0; l < LAYERS; ++l) {
+        TRY(run(f, g_ycontract(f->fs, f->T1, f->T2, B), 48 * 128, sz1, sz2));
+        TRY(run(f, g_zcontract(f->fs, f->T2, f->X3[0], B), 48 * 128, sz2, sz3));
+        TRY(run(f, g_mix(f->X3[0], f->rb[l], f->Y, B, false), sz3, int64_t(NMODES) * 4096, sz3, 4, 2));
+        TRY(run(f, g_zexpand(f->gs, f->Y, f->T2, B), 128 * 48, sz3, sz2));
+        TRY(run(f, g_yexpand(f->gs, f->T2, f->T1, B), 128 * 48, sz2, sz1));
+        a.act = v;
+        a.w = f->wb[l];
+        a.bias = f->prm + off_b(l);
+        if (l < LAYERS - 1) {
+            float* nv = (v == f->V[0]) ? f->V[1] : f->V[0];
+            a.vout = nv;
+            hipLaunchKernelGGL(k_line_fwd, dim3((lines + 3) / 4), dim3(256), 0, f->cur, a);
+            v = nv;
+        } else {
+            hipLaunchKernelGGL(k_line_proj, dim3((lines + 3) / 4), dim3(256), 0, f->cur, a);
+        }
+        TRY(launched());
+    }
+    return TF_OK;
 }
 
 tf_status forward(tf_fno* f, const float* params, const float* hw, int B, float* out) {
@@ -1089,14 +1505,14 @@ tf_status backward(tf_fno* f, const float* params, const float* hw, const float*
         GemmArgs a{opnd(f->V[3], plain(1), plain(C), int64_t(CHUNK) * C, NODE_SZ, 0, C),
                    opnd(f->ghT, plain(1), plain(N3), CHUNK, int64_t(HID) * N3, 1),
                    res(f->part, plain(HID), plain(1), 33 * HID, int64_t(NCHUNK) * 33 * HID), 33, HID, CHUNK};
-        TRY(run(f, Gemm{a, NCHUNK, B, launch<64, 128, 4, float, bf16, false>}, szN, szH, szP));
+        TRY(run(f, Gemm{a, NCHUNK, B, launch<64, 128, 4, float, bf16, false>}, szN, szH, szP, 4, 2));
         TRY(reduce_into(f, B * NCHUNK, 33 * HID, f->grad + OFF_P1));
     }
     {   // [P2; c2] = [h | 1]^T dL/dout
         GemmArgs a{opnd(f->hT, plain(N3), plain(1), CHUNK, int64_t(HID) * N3, 1, HID),
                    opnd(f->gout, plain(1), plain(N3), CHUNK, OUT_SZ, 1),
                    res(f->part, plain(NOUT), plain(1), 129 * NOUT, int64_t(NCHUNK) * 129 * NOUT), 129, NOUT, CHUNK};
-        TRY(run(f, Gemm{a, NCHUNK, B, launch<32, 32, 1, bf16, float, false>}, szH, szO, szP));
+        TRY(run(f, Gemm{a, NCHUNK, B, launch<32, 32, 1, bf16, float, false>}, szH, szO, szP, 2, 4));
         // per-sample gradient of the effective head, then through the head weights
         TRY(reduce_into(f, NCHUNK, 129 * NOUT, f->geff, B));
         const int n = (HID + 1) * NOUT * f->nb;
@@ -1124,7 +1540,7 @@ tf_status backward(tf_fno* f, const float* params, const float* hw, const float*
             hipLaunchKernelGGL(k_fold_r, dim3((n + 255) / 256), dim3(256), 0, f->cur, f->gstar, f->grad + off_r(l));
             TRY(launched());
         }
-        TRY(run(f, g_mix(f->Y, f->rb[l], f->Y2, B, true), sz3, int64_t(NMODES) * 4096, sz3));
+        TRY(run(f, g_mix(f->Y, f->rb[l], f->Y2, B, true), sz3, int64_t(NMODES) * 4096, sz3, 4, 2));
         // adjoint of the forward transform, then the x line with the pointwise branch
         TRY(run(f, g_zexpand(f->fsT, f->Y2, f->T2, B), 128 * 48, sz3, sz2));
         TRY(run(f, g_yexpand(f->fsT, f->T2, f->T1, B), 128 * 48, sz2, sz1));

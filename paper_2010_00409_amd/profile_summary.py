@@ -19,7 +19,10 @@ COPY_BYTES = 1 << 30
 
 
 def _short(name):
+    if "k_gemm" in name:                      # surrogate GEMM: keep the tile shape and types
+        return "k_gemm<" + name.split("k_gemmI", 1)[-1].split("EEvNS", 1)[0] + ">"
     for key in ("k_z_fast", "k_col_fast", "k_x_forward", "k_x_inverse", "k_init_map", "k_readout",
+                "k_lift_x", "k_line_fwd", "k_line_proj", "k_lineout", "k_proj", "k_head_eff",
                 "k_col", "k_z", "k_sumsq", "k_reduce", "copy"):
         if key in name:
             return key

@@ -117,7 +117,14 @@ def test_forward_matches_oracle():
     assert rel(fno.forward(P0, pb, HP), ref) > 10 * FORWARD_TOL
 
 
-def test_training_surrogate_forward_equals_inference_forward():
+# The fused inference kernels feed the next contraction from registers in a
+# relabelled k order and compute the last layer transposed, so the fp32 sums
+# differ from the training path in order only; single bf16 rounding flips
+# (2^-9 relative) downstream keep the difference far below the oracle tolerance.
+INFER_VS_TRAIN_TOL = 1e-3
+
+
+def test_fused_inference_forward_matches_training_forward():
     P = make_params(5)
     pb = np.random.default_rng(6).uniform(size=(2, 8))
     a = run_forward(P, pb)
@@ -126,7 +133,9 @@ def test_training_surrogate_forward_equals_inference_forward():
         pd = torch.from_numpy(pb.astype(np.float32)).cuda()
         out = torch.zeros((2, 6, 64, 64, 64), dtype=torch.float32, device="cuda")
         s.forward(pd, out)
-    assert np.array_equal(out.cpu().numpy().astype(np.float64), a)
+    b = out.cpu().numpy().astype(np.float64)
+    for k in range(2):
+        assert rel(a[k], b[k]) <= INFER_VS_TRAIN_TOL, k
 
 
 def head_weights(rng, B, nb):

@@ -185,12 +185,16 @@ template <int N, int E> struct LGPlan {
     static_assert(N % E == 0 && (N / E) <= 1024, "bad lane-group shape");
 };
 
-// Element n of a lane-group's LDS region sits at base[n * S + (n >> 5) * S2]:
-// S2 = 1 adds one pad slot every 32 elements (contiguous regions), S > 1
+// Element n of a lane-group's LDS region sits at base[n * S + pad(n)]:
+// S2 = 1 adds one pad slot every 32 elements, S2 = 8 one every 8 elements
+// (contiguous regions; the finer pad spreads the 8-element runs of the
+// radix-8 Stockham writes over distinct banks), S2 = 0 none; S > 1
 // interleaves the regions of neighbouring groups (column tiles).
 template <int N, int S, int S2> struct LgAt {
-    __device__ __forceinline__ static int at(int n) { return n * S + (n >> 5) * S2; }
-    static constexpr int span = (N - 1) * S + ((N - 1) >> 5) * S2 + 1;
+    static constexpr int PSH = S2 == 8 ? 3 : 5;
+    static constexpr int PAD = S2 == 8 ? 1 : S2;
+    __device__ __forceinline__ static int at(int n) { return n * S + (n >> PSH) * PAD; }
+    static constexpr int span = (N - 1) * S + ((N - 1) >> PSH) * PAD + 1;
 };
 
 template <typename T, int N, int E, int R, int NS, int DIR, int S, int S2, int TWN>

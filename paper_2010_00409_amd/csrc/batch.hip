@@ -330,8 +330,9 @@ tf_status tf_batch_create(const tf_grid* grids, const tf_pulse* pulses, int32_t 
                 st = fail(TF_EINVAL, "instance " + std::to_string(i) + ": spectral pulse has no samples above w = 0");
                 break;
             }
-            st = alloc(&b->tabs[i], tab.size() * sizeof(double));
-            if (st == TF_OK && hipMemcpy(b->tabs[i], tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) !=
+            const std::vector<double> dtab = spectral_device_table(&pulses[i], tab);
+            st = alloc(&b->tabs[i], dtab.size() * sizeof(double));
+            if (st == TF_OK && hipMemcpy(b->tabs[i], dtab.data(), dtab.size() * sizeof(double), hipMemcpyHostToDevice) !=
                                    hipSuccess)
                 st = fail(TF_EDEVICE, "spectral table upload failed");
             b->pdev[i].nfreq = (int)(tab.size() / 3);

@@ -136,6 +136,23 @@ inline void spectral_table(const tf_pulse* p, std::vector<double>& tab, double& 
     }
 }
 
+// Device form of the sampled spectrum: the kept samples are uniformly spaced
+// (w_m = w0 + m dw), so sum_m a_m exp(i (phi_m - w_m zeta)) is
+// exp(-i w0 zeta) times a polynomial in exp(-i dw zeta) with coefficients
+// c_m = a_m exp(i phi_m).  Layout {w0, dw, re c_0, im c_0, ...}.
+inline std::vector<double> spectral_device_table(const tf_pulse* p, const std::vector<double>& tab) {
+    const int K = (int)(tab.size() / 3);
+    const double w0 = 2.0 * M_PI / p->wavelength;
+    std::vector<double> d(2 + 2 * K);
+    d[0] = K > 0 ? tab[0] : 0.0;
+    d[1] = w0 * p->bandwidth * (2.0 * 4.0 / p->nfreq);      // w0 delta (2X / M), X = 4
+    for (int m = 0; m < K; ++m) {
+        d[2 + 2 * m] = tab[3 * m + 1] * std::cos(tab[3 * m + 2]);
+        d[3 + 2 * m] = tab[3 * m + 1] * std::sin(tab[3 * m + 2]);
+    }
+    return d;
+}
+
 inline std::vector<double> twiddle_table(int n) {
     std::vector<double> t(2 * n);
     for (int e = 0; e < n; ++e) {
@@ -191,6 +208,7 @@ inline PulseDev pulse_dev(const tf_pulse* pulse, const tf_pulse_info& g) {
         p.amp[0] = 1.0;
         p.d[0][0] = 1.0; p.d[0][1] = 0.0; p.d[0][2] = 0.0;
         p.phase_off[0] = 0.0;
+        p.phase_off[1] = 0.0;
     } else {
         const double c = std::cos(pulse->pol_angle), sn = std::sin(pulse->pol_angle);
         const double e = pulse->ellipticity;
@@ -202,6 +220,10 @@ inline PulseDev pulse_dev(const tf_pulse* pulse, const tf_pulse_info& g) {
         p.amp[1] = e / nrm;
         p.d[1][0] = 0.0; p.d[1][1] = -sn; p.d[1][2] = c;
         p.phase_off[1] = 0.5 * M_PI;
+    }
+    for (int k = 0; k < 2; ++k) {
+        p.cph[k] = std::cos(p.cep + p.phase_off[k] + 0.5 * M_PI);
+        p.sph[k] = std::sin(p.cep + p.phase_off[k] + 0.5 * M_PI);
     }
     return p;
 }

@@ -24,24 +24,36 @@ __device__ double u_ts(double alpha, const PulseDev& p) {
 }
 
 // Longitudinal profile with carrier, zeta inside [-L/2, L/2] (checked by the
-// caller): cos^2 envelope of Eq. (7), Gaussian envelope of Sec. III.B.1, or
-// the sampled spectrum (Re sum a_m cos(phase + pi/2 + phi_m - w_m zeta)) / gnorm.
-__device__ double u_l(double zeta, double phase, const PulseDev& p) {
+// caller), for the cos^2 envelope of Eq. (7) and the Gaussian envelope of
+// Sec. III.B.1.
+__device__ double u_l_closed(double zeta, double phase, const PulseDev& p) {
     if (p.envelope == 0) {
         const double c = cos(M_PI * zeta / p.L);
         return sin(2.0 * M_PI * zeta / p.lambda - phase) * (c * c);
     }
-    if (p.envelope == 1) {
-        const double nl = p.ncycles * p.lambda;
-        return sin(2.0 * M_PI * zeta / p.lambda - phase) * exp(-zeta * zeta * log(4.0) / (nl * nl));
+    const double nl = p.ncycles * p.lambda;
+    return sin(2.0 * M_PI * zeta / p.lambda - phase) * exp(-zeta * zeta * log(4.0) / (nl * nl));
+}
+
+// Sampled spectrum: S(zeta) = sum_m a_m exp(i (phi_m - w_m zeta)), evaluated
+// as exp(-i w0 zeta) P(exp(-i dw zeta)) with P(z) = sum_m c_m z^m by Horner's
+// rule (|z| = 1, so the rounding stays at a few ulps of sum |c_m|).  The
+// profile of a part with carrier phase ph is Re[exp(i (ph + pi/2)) S] / gnorm.
+__device__ void spectral_sum(double zeta, const PulseDev& p, double& sr, double& si) {
+    const double* c = p.spec + 2;
+    const int K = p.nfreq;
+    double zs, zc, es, ec;
+    sincos(-p.spec[1] * zeta, &zs, &zc);
+    sincos(-p.spec[0] * zeta, &es, &ec);
+    double pr = c[2 * (K - 1)], pim = c[2 * (K - 1) + 1];
+    for (int m = K - 2; m >= 0; --m) {
+        const double tr = pr * zc - pim * zs;
+        const double ti = pr * zs + pim * zc;
+        pr = c[2 * m] + tr;
+        pim = c[2 * m + 1] + ti;
     }
-    double acc = 0.0;
-    const double ph0 = phase + 0.5 * M_PI;
-    for (int m = 0; m < p.nfreq; ++m) {
-        const double w = p.spec[3 * m], a = p.spec[3 * m + 1], phi = p.spec[3 * m + 2];
-        acc += a * cos(ph0 + phi - w * zeta);
-    }
-    return acc / p.gnorm;
+    sr = pr * ec - pim * es;
+    si = pr * es + pim * ec;
 }
 
 // Adds the unmapped pulse at physical point (x, y, z) to e, b.
@@ -53,8 +65,12 @@ __device__ void add_pulse(double x, double y, double z, const PulseDev& p, doubl
     const double alpha = atan2(rho, -x);                    // angle from the -x axis
     if (!(alpha <= p.alpha_max)) return;
     const double ts = u_ts(alpha, p);
+    double sr = 0.0, si = 0.0;
+    if (p.envelope == 2) spectral_sum(zeta, p, sr, si);     // shared by both polarisation parts
     for (int k = 0; k < p.nparts; ++k) {
-        const double u = p.A / R * u_l(zeta, p.cep + p.phase_off[k], p) * ts;
+        const double ul = p.envelope == 2 ? (p.cph[k] * sr - p.sph[k] * si) / p.gnorm
+                                          : u_l_closed(zeta, p.cep + p.phase_off[k], p);
+        const double u = p.A / R * ul * ts;
         const double* d = p.d[k];
         // s1 ~ d x R, s0 ~ R x (d x R)
         const double c1x = d[1] * z - d[2] * y, c1y = d[2] * x - d[0] * z, c1z = d[0] * y - d[1] * x;

@@ -71,7 +71,10 @@ struct PulseDev {
     double gnorm;                 // spectral normalisation
     int nparts;                   // 1 or 2 polarisation parts
     double amp[2], d[2][3], phase_off[2];
-    const double* spec;           // nfreq x {w, a, phi} (spectral only)
+    double cph[2], sph[2];        // cos, sin of cep + phase_off + pi/2 (spectral carrier phase)
+    // spectral only: {w0, dw, then c_m = a_m exp(i phi_m) as re, im} for the
+    // nfreq kept samples w_m = w0 + m dw
+    const double* spec;
 };
 
 struct GridDev {

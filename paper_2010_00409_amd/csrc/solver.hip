@@ -279,8 +279,9 @@ tf_status tf_set_pulse(tf_solver* s, const tf_pulse* pulse, tf_pulse_info* info)
             TF_HIP(hipFree(s->pulse_tab));
             s->pulse_tab = nullptr;
         }
-        TF_HIP(hipMalloc(&s->pulse_tab, tab.size() * sizeof(double)));
-        TF_HIP(hipMemcpyAsync(s->pulse_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice,
+        const std::vector<double> dtab = spectral_device_table(pulse, tab);
+        TF_HIP(hipMalloc(&s->pulse_tab, dtab.size() * sizeof(double)));
+        TF_HIP(hipMemcpyAsync(s->pulse_tab, dtab.data(), dtab.size() * sizeof(double), hipMemcpyHostToDevice,
                               s->stream));
         TF_HIP(hipStreamSynchronize(s->stream));
         p.nfreq = (int)(tab.size() / 3);

@@ -275,7 +275,7 @@ tf_status tf_tune(const int32_t* sizes, int32_t n, int32_t precision, const char
  * This surrogate is trained on the solver's focal windows and maps eight
  * pulse and optics parameters, each normalised to [0, 1], to the
  * six-component field on a 64^3 focal window.  The plain solver stays its
- * fallback and the judge of its error.
+ * fallback and the reference for its error.
  *
  * Architecture (fixed): lift [p, x, y, z] -> 32 channels (x, y, z the node
  * coordinates scaled to [-1, 1)); three Fourier layers

@@ -17,6 +17,6 @@ Modules
 ``fno``      Fourier neural operator forward/backward (parity unpinned by
              the paper; pinned by finite differences)
 
-Readings taken where the paper is silent or garbled are listed in each
-module's docstring (Q1..Q23 are the identifiers used in the design doc).
+Readings taken where the paper is silent or garbled are stated in each
+module's docstring.
 """

@@ -8,12 +8,12 @@ the indicator I_S(t)(R), with l(t) = -R_max + c t and r(t) = -R_min + c t:
 
   r < 0:          0 if R >= -l or R < -r or x > 0
   l <= 0 <= r:    0 if x < 0 and R > L
-                  0 if x >= 0 and R > r       (Q11: printed "R > l")
+                  0 if x >= 0 and R > r       (printed with l: read as r)
   l > 0:          0 if R <= l or R > r or x < 0
   otherwise 1.
 
-Readings: {a} = a - floor(a) (Q8); t is the time since the start of the run,
-so the geometric focus is reached at t = R0/c (Q12).  The focal window is
+Readings: {a} = a - floor(a); t is the time since the start of the run,
+so the geometric focus is reached at t = R0/c.  The focal window is
 node-aligned: its centre snaps to node floor((c - min)/d + 1/2), node i of
 the window is centre + i - w//2 (unwrapped), x wraps modulo nx (this is T
 on nodes) and y, z must stay inside the grid (no transverse wrap).
@@ -26,7 +26,7 @@ C_LIGHT = 1.0
 
 
 def indicator(x, y, z, t, R_min, R_max):
-    """I_S(t)(R) of Eq. (15) with the Q11 reading of its third case."""
+    """I_S(t)(R) of Eq. (15), its third case read as x >= 0 and R > r."""
     x, y, z = np.broadcast_arrays(*(np.asarray(v, dtype=np.float64) for v in (x, y, z)))
     R = np.sqrt(x * x + y * y + z * z)
     L = R_max - R_min

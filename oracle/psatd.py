@@ -13,14 +13,14 @@ applied to the Fourier coefficients of E and B, followed by the inverse
 transform.  The longitudinal part of E is removed at every step, as the
 paper does (Sec. II.A, text before Eq. (3)).
 
-Readings where the paper is silent (identifiers as in the design doc):
+Readings where the paper is silent:
 
-* Q1  the forward transform uses exp(-i k.x) (so grad -> +ik);
-* Q2  k_hat := 0 at k = 0, so the DC mode is left unchanged;
-* Q3  on an even axis the Nyquist index contributes 0 to k (to |k| and to
-      k_hat), which keeps M(-k) = conj M(k) and so keeps fields real;
-* Q4  ``project_b=True`` also removes the longitudinal part of B (used once
-      at initialisation; Eq. (4) alone would make it oscillate as C).
+* the forward transform uses exp(-i k.x) (so grad -> +ik);
+* k_hat := 0 at k = 0, so the DC mode is left unchanged;
+* on an even axis the Nyquist index contributes 0 to k (to |k| and to
+  k_hat), which keeps M(-k) = conj M(k) and so keeps fields real;
+* ``project_b=True`` also removes the longitudinal part of B (used once
+  at initialisation; Eq. (4) alone would make it oscillate as C).
 
 Field arrays have shape (3, nz, ny, nx): component, z, y, x with x fastest,
 matching the library's [component][z][y][x] layout.
@@ -34,7 +34,7 @@ C_LIGHT = 1.0
 
 
 def signed_index(n):
-    """Signed mode number of each DFT index on an axis of length n (Q3)."""
+    """Signed mode number of each DFT index on an axis of length n (Nyquist -> 0)."""
     m = np.arange(n)
     s = np.where(m <= (n - 1) // 2, m, m - n).astype(np.float64)
     if n % 2 == 0:
@@ -78,7 +78,7 @@ def update(Eh, Bh, k, dt, project_b=False, c=C_LIGHT):
     kappa = np.sqrt(kx * kx + ky * ky + kz * kz)
     nz = kappa > 0
     inv = np.where(nz, 1.0 / np.where(nz, kappa, 1.0), 0.0)
-    kh = (kx * inv, ky * inv, kz * inv)                        # Q2: 0 at k = 0
+    kh = (kx * inv, ky * inv, kz * inv)                        # k_hat = 0 at k = 0
     C = np.cos(c * kappa * dt)
     S = np.sin(c * kappa * dt)
     kE = kh[0] * Eh[0] + kh[1] * Eh[1] + kh[2] * Eh[2]
@@ -97,7 +97,7 @@ def step_direct(E, B, spacing, dt, project_b=False):
     """One step with the full complex direct DFT (oracle O1).
 
     Returns real float64 arrays; asserts that the imaginary residue of the
-    inverse is at rounding level (pins the Nyquist reading Q3)."""
+    inverse is at rounding level (pins the Nyquist reading)."""
     shape = E.shape[1:]
     k = wavevector(shape, spacing, half_x=False)
     Eh = [dft.dftn(E[a]) for a in range(3)]
@@ -109,7 +109,7 @@ def step_direct(E, B, spacing, dt, project_b=False):
         re = np.stack([x.real for x in comp])
         im = np.stack([x.imag for x in comp])
         scale = max(np.abs(re).max(), 1e-300)
-        assert np.abs(im).max() <= 1e-11 * scale, "non-real inverse (Q3)"
+        assert np.abs(im).max() <= 1e-11 * scale, "non-real inverse (Nyquist reading)"
         out.append(re)
     return out[0], out[1]
 
@@ -123,7 +123,7 @@ def step_fft(E, B, spacing, dt, nsteps=1, project_b_first=False,
     """``nsteps`` steps of dt with scipy's real FFT (oracle O2).
 
     Every step is forward rfftn -> Eqs. (3)-(4) -> inverse irfftn, as the
-    method's iteration.  ``project_b_first`` applies Q4 in the first step.
+    method's iteration.  ``project_b_first`` removes longitudinal B in the first step.
     """
     workers = workers or _workers()
     shape = E.shape[1:]

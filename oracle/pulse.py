@@ -18,21 +18,21 @@ Closed forms followed:
   sum over the preimages x + n D of every layer node (superposition of
   replicas, the remark after Eq. (12)).
 
-Readings (identifiers as in DESIGN.md):
+Readings:
 
-* Q5  s1 = normalise(d x R), s0 = normalise(R x (d x R)) = component of d
-      perpendicular to R; fields are 0 where d is parallel to R.
-* Q6  alpha = angle from the -x axis = atan2(sqrt(y^2+z^2), -x).
-* Q7  the first window of Eq. (5) is half-open, [0, theta - eps/2).
-* Q9  layer nodes sum the contributions of all their preimages.
-* Q10 x_min is shifted onto the node grid so the origin is a node.
-* Q13 c = 1; fields in CGS form; A normalises the cycle-averaged power
-      through the cap to P0.  Gaussian transverse: A = sqrt(4 P0 / F(theta0)).
-* Q17 spectral envelope: g(zeta) = Re sum_m a_m exp(i phi_m) exp(-i w_m zeta)
-      on M frequency samples; a(w) = G(w - w0) - G(w + w0), G(x) =
-      exp(-(x/(delta w0))^2) (antisymmetrised so no DC radiates);
-      phi = phase + pi/2 + GDD (w-w0)^2/2 + TOD (w-w0)^3/6; normalised so
-      max |g| over zeta_j = j lambda/128 inside the window is 1.
+* s1 = normalise(d x R), s0 = normalise(R x (d x R)) = component of d
+  perpendicular to R; fields are 0 where d is parallel to R.
+* alpha = angle from the -x axis = atan2(sqrt(y^2+z^2), -x).
+* the first window of Eq. (5) is half-open, [0, theta - eps/2).
+* layer nodes sum the contributions of all their preimages.
+* x_min is shifted onto the node grid so the origin is a node.
+* c = 1; fields in CGS form; A normalises the cycle-averaged power
+  through the cap to P0.  Gaussian transverse: A = sqrt(4 P0 / F(theta0)).
+* spectral envelope (not in the paper): g(zeta) = Re sum_m a_m exp(i phi_m)
+  exp(-i w_m zeta) on M frequency samples; a(w) = G(w - w0) - G(w + w0),
+  G(x) = exp(-(x/(delta w0))^2) (antisymmetrised so no DC radiates);
+  phi = phase + pi/2 + GDD (w-w0)^2/2 + TOD (w-w0)^3/6; normalised so
+  max |g| over zeta_j = j lambda/128 inside the window is 1.
 * Gaussian and spectral envelopes are cut by the window [-L/2, L/2] of
   Eq. (6), L being the descriptor's support length.
 * Elliptical polarisation: E = a1 u(phase) s0(d1) + a2 u(phase+pi/2) s0(d2)
@@ -93,7 +93,7 @@ def geometry(p):
 
 
 def u_ts(alpha, p, g):
-    """Transverse profile: Eq. (5) (flat-top, Q7) or exp(-a^2/theta0^2)."""
+    """Transverse profile: Eq. (5) (flat-top, first window half-open) or exp(-a^2/theta0^2)."""
     th = g["theta"]
     if p["transverse"] == "flattop":
         eps = p["eps"]
@@ -105,7 +105,7 @@ def u_ts(alpha, p, g):
 
 
 def spectral_samples(p):
-    """Frequency samples (w_m, a_m, chirp phase phi_m) of the Q17 spectrum."""
+    """Frequency samples (w_m, a_m, chirp phase phi_m) of the sampled spectrum."""
     M = int(p["nfreq"])
     w0 = 2.0 * np.pi * C_LIGHT / p["wavelength"]
     dlt = p["bandwidth"]
@@ -131,7 +131,7 @@ def g_spectral_raw(zeta, p, phase):
 
 
 def spectral_norm(p):
-    """max |g| over zeta_j = j lambda/128 inside the window (Q17)."""
+    """max |g| over zeta_j = j lambda/128 inside the window."""
     lam = p["wavelength"]
     h = lam / NORM_SAMPLES_PER_WAVELENGTH
     jmax = int(math.floor(0.5 * p["L"] / h))
@@ -151,7 +151,7 @@ def u_l(zeta, p, phase, gnorm=None):
         n = p["ncycles"]
         val = (np.sin(2.0 * np.pi * zeta / lam - phase)
                * np.exp(-zeta * zeta * math.log(4.0) / (n * lam) ** 2))
-    elif env == "spectral":                                    # Q17
+    elif env == "spectral":                                    # sampled spectrum
         if gnorm is None:
             gnorm = spectral_norm(p)
         val = g_spectral_raw(zeta, p, phase) / gnorm
@@ -180,7 +180,7 @@ def phasor_weights(p, nbasis):
     Every envelope is u_l(zeta; phase) = Re[exp(i sigma phase) G(zeta)] with
     sigma = +1 for the spectral envelope (its phase enters as +phase) and -1
     for the cos^2 and Gaussian envelopes (sin(k zeta - phase), Eq. (7)); the
-    spectral one is divided by gnorm (Q17), the others by 1.  The polarisation
+    spectral one is divided by gnorm, the others by 1.  The polarisation
     parts are (1/n) d1 at phase CEP and (e/n) d2 at CEP + pi/2, n = sqrt(1+e^2).
     Since the solver is linear, with z = exp(i sigma CEP):
       nbasis 1: [1]                                          (plain output)
@@ -223,7 +223,7 @@ def fields_at(x, y, z, p, g, gnorm=None):
     B = np.zeros((3, x.size))
     R = np.sqrt(x * x + y * y + z * z)
     rho = np.sqrt(y * y + z * z)
-    alpha = np.arctan2(rho, -x)                                # Q6
+    alpha = np.arctan2(rho, -x)                                # angle from -x
     zeta = R - g["R0"]
     support = (zeta >= -0.5 * g["L"]) & (zeta <= 0.5 * g["L"]) & (alpha <= g["alpha_max"])
     sel = np.nonzero(support)
@@ -235,7 +235,7 @@ def fields_at(x, y, z, p, g, gnorm=None):
     ts = u_ts(al, p, g)
     for amp, d, ph in pol_parts(p):
         u = g["A"] / Rs * u_l(ze, p, p["cep"] + ph, gnorm) * ts
-        # s1 ~ d x R, s0 ~ R x (d x R)   (Q5)
+        # s1 ~ d x R, s0 ~ R x (d x R)
         c1 = (d[1] * zs - d[2] * ys, d[2] * xs - d[0] * zs, d[0] * ys - d[1] * xs)
         n1 = np.sqrt(c1[0] * c1[0] + c1[1] * c1[1] + c1[2] * c1[2])
         c0 = (ys * c1[2] - zs * c1[1], zs * c1[0] - xs * c1[2], xs * c1[1] - ys * c1[0])
@@ -250,7 +250,7 @@ def fields_at(x, y, z, p, g, gnorm=None):
 
 def layer_grid(p, n, spacing):
     """Periodic layer of Sec. II.C: D = nx dx, x_min = -R_min - D shifted onto
-    the node grid so the origin is a node (Q10); y, z centred on the axis."""
+    the node grid so the origin is a node; y, z centred on the axis."""
     nx, ny, nz = n
     dx, dy, dz = spacing
     g = geometry(p)
@@ -271,7 +271,7 @@ def preimage_range(grid, g):
 
 def init_fields_at(p, grid, iz, iy, ix):
     """E, B at the layer nodes (iz, iy, ix): sum over preimages x + n D of
-    the pulse (Eq. (13) inverted; Q9).  Returns two (3, npts) arrays."""
+    the pulse (Eq. (13) inverted; preimages superpose).  Returns two (3, npts) arrays."""
     g = geometry(p)
     gnorm = spectral_norm(p) if p["envelope"] == "spectral" else None
     D = grid["nx"] * grid["dx"]

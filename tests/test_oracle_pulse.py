@@ -242,7 +242,7 @@ def test_overlapping_replicas_superpose():
     assert np.allclose(E, ref, atol=1e-13)
 
 
-# --- spectral pulse (Q17) -----------------------------------------------------
+# --- spectral pulse (sampled spectrum) -----------------------------------------------------
 
 def test_spectral_envelope_unchirped_is_a_gaussian_pulse():
     p = configs.pulse(envelope="spectral", bandwidth=1 / 3, L=12.0, cep=0.7)
@@ -282,7 +282,7 @@ def test_indicator_cases():
     assert ind(-16.0, 0.0) == 1.0 and ind(-14.9, 0.0) == 0.0 and ind(16.0, 0.0) == 0.0
     assert ind(-8.0, 8.0) == 1.0 and ind(-6.9, 8.0) == 0.0
     assert ind(-1.5, 16.0) == 1.0 and ind(-2.5, 16.0) == 0.0     # x < 0: R <= L
-    assert ind(0.9, 16.0) == 1.0 and ind(1.1, 16.0) == 0.0       # x >= 0: R <= r (Q11)
+    assert ind(0.9, 16.0) == 1.0 and ind(1.1, 16.0) == 0.0       # x >= 0: R <= r
     assert ind(10.0, 26.0) == 1.0 and ind(-10.0, 26.0) == 0.0 and ind(8.9, 26.0) == 0.0
 
 

@@ -86,7 +86,7 @@ def test_P1_single_plane_wave_is_advanced_exactly(dt):
 
 
 def test_P1_direction_of_propagation_fixes_fft_sign():
-    # E = y cos(kx), B = z cos(kx) moves towards +x (Q1): after a quarter
+    # E = y cos(kx), B = z cos(kx) moves towards +x (forward transform exp(-i k.x)): after a quarter
     # period the field is y sin(kx).
     g = configs.cube_grid(16, 0.25)
     x, _, _ = planewaves.node_coords(g)
@@ -135,7 +135,7 @@ def test_P4_longitudinal_fields_are_removed():
     E1, B1 = psatd.step_fft(E, B, spacing(g), 0.4, project_b_first=False)
     dE1, dB1 = psatd.max_divergence(E1, B1, spacing(g))
     assert dE1 < 1e-13          # Eq. (3) removes k(k.E) every step
-    assert dB1 > 0.1            # Eq. (4) alone keeps longitudinal B (Q4)
+    assert dB1 > 0.1            # Eq. (4) alone keeps longitudinal B
     E2, B2 = psatd.step_fft(E, B, spacing(g), 0.4, project_b_first=True)
     assert max(psatd.max_divergence(E2, B2, spacing(g))) < 1e-13
 
@@ -189,7 +189,7 @@ def test_P9_P10_direct_dft_step_is_real_and_matches_fft_step():
 
 
 def test_nyquist_modes_with_signed_reading_would_break_reality():
-    # The Q3 reading (Nyquist -> 0) is what keeps the step real: giving the
+    # The Nyquist -> 0 reading is what keeps the step real: giving the
     # Nyquist index the value -N/2 produces an O(1) imaginary residue.
     n = 8
     s = psatd.signed_index(n)

@@ -142,50 +142,52 @@ __device__ __forceinline__ void ld4(const bf16* p, float v[4]) {
 
 // Stage a ROWS x 32 slice of an operand in LDS as bf16 (hi and, for SPLIT,
 // lo parts), k contiguous.  "Rows" are the M index of A or the N index of B.
+// Each thread owns one row and 8 consecutive k and stores them with one
+// 16-byte LDS write per part.  Neighbouring threads take neighbouring k
+// groups when k is the contiguous index in memory (two 16-byte global loads
+// when aligned), else neighbouring rows (coalesced 4-byte loads); either way
+// the 16-byte writes of a quarter-wave start 20 banks apart (row pitch 80 B)
+// or are contiguous, so they do not collide.
 template <int ROWS, int NT, typename TT, bool SPLIT, bool IS_B>
 __device__ __forceinline__ void stage(bf16* s0, bf16* s1, const TT* P, const Operand& o, int r0, int k0, int nrows,
                                       int K) {
-    constexpr int BK = 32, PITCH = BK + 8;
-    const int tid = threadIdx.x;
-    auto put = [&](int rr, int kk, float v) {
-        const bf16 hi = (bf16)v;
-        s0[rr * PITCH + kk] = hi;
-        if constexpr (SPLIT) s1[rr * PITCH + kk] = (bf16)(v - (float)hi);
-    };
+    constexpr int BK = 32, PITCH = BK + 8, KG = BK / 8;
     auto off = [&](int gr, int gk) -> int64_t {
         return IS_B ? ixoff(o.r, gk) + ixoff(o.c, gr) : ixoff(o.r, gr) + ixoff(o.c, gk);
     };
-    auto one = [&](int gr) { return !P || (!IS_B && gr >= o.ones_from); };
-    if (o.vec) {
-        if (o.fast_k) {
-            for (int e = tid; e < ROWS * BK / 4; e += NT) {
-                const int rr = e / (BK / 4), kk = 4 * (e % (BK / 4));
-                const int gr = r0 + rr, gk = k0 + kk;
-                float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-                if (gr < nrows && gk < K) ld4(P + off(gr, gk), v);
+    for (int t = threadIdx.x; t < ROWS * KG; t += NT) {
+        int rr, kg;
+        if (o.fast_k) { rr = t / KG; kg = t % KG; }
+        else          { rr = t % ROWS; kg = t / ROWS; }
+        const int gr = r0 + rr, gk0 = k0 + 8 * kg;
+        float v[8];
+        if (gr >= nrows) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) put(rr, kk + q, v[q]);
-            }
+            for (int e = 0; e < 8; ++e) v[e] = 0.0f;
+        } else if (!P || (!IS_B && gr >= o.ones_from)) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = gk0 + e < K ? 1.0f : 0.0f;
+        } else if (o.vec && o.fast_k && gk0 + 8 <= K) {
+            ld4(P + off(gr, gk0), v);
+            ld4(P + off(gr, gk0 + 4), v + 4);
+        } else if (gk0 + 8 <= K) {
+            const int64_t orow = IS_B ? ixoff(o.c, gr) : ixoff(o.r, gr);
+            const Ix kmap = IS_B ? o.r : o.c;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = ldf(P + orow + ixoff(kmap, gk0 + e));
         } else {
-            for (int e = tid; e < ROWS * BK / 4; e += NT) {
-                const int rr = 4 * (e % (ROWS / 4)), kk = e / (ROWS / 4);
-                const int gr = r0 + rr, gk = k0 + kk;
-                float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-                if (gr < nrows && gk < K) ld4(P + off(gr, gk), v);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) put(rr + q, kk, v[q]);
-            }
+            for (int e = 0; e < 8; ++e) v[e] = gk0 + e < K ? ldf(P + off(gr, gk0 + e)) : 0.0f;
         }
-        return;
-    }
-    for (int e = tid; e < ROWS * BK; e += NT) {
-        int rr, kk;
-        if (o.fast_k) { rr = e / BK; kk = e % BK; }
-        else          { rr = e % ROWS; kk = e / ROWS; }
-        const int gr = r0 + rr, gk = k0 + kk;
-        float v = 0.0f;
-        if (gr < nrows && gk < K) v = one(gr) ? 1.0f : ldf(P + off(gr, gk));
-        put(rr, kk, v);
+        bf16x8 hi, lo;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const bf16 h = (bf16)v[e];
+            hi[e] = h;
+            lo[e] = (bf16)(v[e] - (float)h);
+        }
+        *(bf16x8*)&s0[rr * PITCH + 8 * kg] = hi;
+        if constexpr (SPLIT) *(bf16x8*)&s1[rr * PITCH + 8 * kg] = lo;
     }
 }
 
@@ -1046,7 +1048,7 @@ inline Operand opnd(const void* p, Ix r, Ix c, int64_t b1, int64_t b2, int fast_
 // Whether groups of 4 along the operand's contiguous index are contiguous and
 // aligned for 4-element loads (rows x cols is the operand's shape).
 inline bool vec_ok(const Operand& o, int rows, int cols, bool is_b, size_t elem) {
-    if (!o.p || o.ones_from < (1 << 30)) return false;
+    if (!o.p || o.ones_from < (1 << 30) || !o.fast_k) return false;
     const bool k_is_row = is_b;                 // A: (M, K); B: (K, N)
     const Ix fast = o.fast_k ? (k_is_row ? o.r : o.c) : (k_is_row ? o.c : o.r);
     const Ix slow = o.fast_k ? (k_is_row ? o.c : o.r) : (k_is_row ? o.r : o.c);

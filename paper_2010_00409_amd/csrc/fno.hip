@@ -733,7 +733,9 @@ __global__ __launch_bounds__(256) void k_line_fwd(InfArgs a) {
 // projection then runs as in k_proj.
 __global__ __launch_bounds__(256) void k_line_proj(InfArgs a) {
     const int lane = threadIdx.x & 63, t = lane & 31, grp = lane >> 5;
-    const int line = blockIdx.x * 4 + (threadIdx.x >> 6);
+    // one wave per half line (32 nodes): twice the independent waves
+    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int line = item >> 1, h = item & 1;
     if (line >= a.nlines) return;
     const int b = line / (N * N), zy = line % (N * N);
     bf16x8 wf[2], lh[2], ll[2];
@@ -750,8 +752,7 @@ __global__ __launch_bounds__(256) void k_line_proj(InfArgs a) {
     const bf16x8* p2k = (const bf16x8*)(a.p2k + int64_t(b) * KSLOTS) + grp * 32 + t;
     const float* c2 = a.c2e + b * NOUT;
     const int64_t base = int64_t(line) * N * C;
-#pragma unroll 1
-    for (int h = 0; h < 2; ++h) {
+    {
         const int x = 32 * h + t;
         f32x16 acc;
 #pragma unroll
@@ -1470,7 +1471,7 @@ tf_status forward_infer(tf_fno* f, const float* params, int B, float* out) {
             hipLaunchKernelGGL(k_line_fwd, dim3((lines + 3) / 4), dim3(256), 0, f->cur, a);
             v = nv;
         } else {
-            hipLaunchKernelGGL(k_line_proj, dim3((lines + 3) / 4), dim3(256), 0, f->cur, a);
+            hipLaunchKernelGGL(k_line_proj, dim3((2 * lines + 3) / 4), dim3(256), 0, f->cur, a);
         }
         TRY(launched());
     }

@@ -100,3 +100,33 @@ def test_layer_grid_matches_oracle(n, d):
         got = tf.tf_layer_grid(p, n, (d, d, d))
         ref = opulse.layer_grid(p, n, (d, d, d))
         assert got == ref
+
+
+def test_surrogate_arguments_are_validated_before_any_hip_call():
+    import ctypes
+    lib = tf.load()
+    h = ctypes.c_void_p()
+    assert lib.tf_fno_create(0, 0, 1, None, ctypes.byref(h)) == tf.TF_EINVAL
+    assert lib.tf_fno_create(129, 0, 1, None, ctypes.byref(h)) == tf.TF_EINVAL
+    assert lib.tf_fno_create(4, 0, 3, None, ctypes.byref(h)) == tf.TF_EINVAL
+    assert lib.tf_fno_create(4, 0, 1, None, None) == tf.TF_EINVAL
+    assert [lib.tf_fno_param_count(k) for k in (0, 1, 2, 3, 4)] == \
+        [-1, lib.tf_fno_param_count(1), lib.tf_fno_param_count(1) + 774, -1, lib.tf_fno_param_count(1) + 2322]
+    assert lib.tf_fno_forward(None, None, None, 1, None) == tf.TF_EINVAL
+    assert lib.tf_fno_infer(None, None, None, 1, None) == tf.TF_EINVAL
+    assert lib.tf_fno_train_step(None, None, None, None, 1, 1e-3, None) == tf.TF_EINVAL
+    assert lib.tf_fno_destroy(None) == tf.TF_OK
+    w = (ctypes.c_double * 4)()
+    assert lib.tf_fno_phasor_weights(ctypes.byref(tf.pulse_struct(configs.pulse())), 3, w) == tf.TF_EINVAL
+    assert lib.tf_fno_phasor_weights(None, 2, w) == tf.TF_EINVAL
+
+
+def test_surrogate_head_weights_of_a_plain_pulse():
+    """Linear polarisation along y, no ellipticity, CEP 0, cos^2 envelope
+    (s = -1, gnorm 1): weights (1, 0, 0, 0) for four basis fields."""
+    import numpy as np
+    w = tf.tf_fno_phasor_weights(configs.pulse(cep=0.0, pol_angle=0.0, ellipticity=0.0), 4)
+    assert np.allclose(w, [1, 0, 0, 0], atol=1e-15)
+    w2 = tf.tf_fno_phasor_weights(configs.pulse(cep=0.5 * np.pi, pol_angle=0.5 * np.pi), 4)
+    # z = exp(-i pi/2) = -i, b = 1: Re(z b) = 0, -Im(z b) = 1
+    assert np.allclose(w2, [0, 0, 0, 1], atol=1e-15)

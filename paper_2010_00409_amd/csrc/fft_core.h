@@ -236,6 +236,64 @@ __device__ __forceinline__ void lg_stage_tw(C2<T> (&x)[E], C2<T>* reg, const C2<
     }
 }
 
+// Two independent lane-group transforms of one shape whose stages share
+// their barriers: both compute, both exchange through their own LDS regions
+// (rega, regb must not overlap), one pair of barriers per stage.
+template <typename T, int N, int E, int R, int NS, int DIR, int S, int S2, int TWN>
+__device__ __forceinline__ void lg_stage_compute(C2<T> (&x)[E], C2<T>* reg, const C2<T>* tw, int u) {
+    constexpr int G = N / E, Q = E / R;
+    constexpr bool LAST = (NS * R == N);
+    using A = LgAt<N, S, S2>;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int j = u + G * q;
+        C2<T> v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = x[q + Q * r];
+        const int jm = j % NS;
+        if constexpr (NS > 1) {
+            constexpr int STEP = (TWN / N) * (N / (NS * R));
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                C2<T> w = tw[r * jm * STEP];
+                if (DIR > 0) w = cconj(w);
+                v[r] = cmul(v[r], w);
+            }
+        }
+        dftR<T, R, DIR>(v);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[q + Q * r] = v[r];
+        } else {
+            const int base = (j / NS) * NS * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r) reg[A::at(base + r * NS)] = v[r];
+        }
+    }
+}
+
+template <typename T, int N, int E, int DIR, int S, int S2, int TWN = N, int ST = 0, int NS = 1>
+__device__ __forceinline__ void lg_fft2(C2<T> (&xa)[E], C2<T> (&xb)[E], C2<T>* rega, C2<T>* regb, const C2<T>* tw,
+                                        int u) {
+    if constexpr (ST < LGPlan<N, E>::nst) {
+        constexpr int R = LGPlan<N, E>::radix(ST);
+        constexpr int G = N / E;
+        using A = LgAt<N, S, S2>;
+        lg_stage_compute<T, N, E, R, NS, DIR, S, S2, TWN>(xa, rega, tw, u);
+        lg_stage_compute<T, N, E, R, NS, DIR, S, S2, TWN>(xb, regb, tw, u);
+        if constexpr (NS * R != N) {
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                xa[e] = rega[A::at(u + G * e)];
+                xb[e] = regb[A::at(u + G * e)];
+            }
+            __syncthreads();
+        }
+        lg_fft2<T, N, E, DIR, S, S2, TWN, ST + 1, NS * R>(xa, xb, rega, regb, tw, u);
+    }
+}
+
 // tw: table of TWN entries exp(-2 pi i e / TWN), TWN a multiple of N.
 template <typename T, int N, int E, int DIR, int S, int S2, int TWN = N, int ST = 0, int NS = 1>
 __device__ __forceinline__ void lg_fft(C2<T> (&x)[E], C2<T>* reg, const C2<T>* tw, int u) {

@@ -1,6 +1,8 @@
 """Benchmark of the headline workload on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-surrogate]
+    python bench.py --workload c4          # batched sweep of 64 uneven grids
+    python bench.py --workload surrogate   # the surrogate section alone
 
 Workload (C3): a 512^3 float32 periodic layer, dx = lambda/12, a two-octave
 single-cycle spectral pulse (f = 0.5, radial polarisation) put on the
@@ -12,8 +14,13 @@ synthetic and generated on the device by the library.
 
 Printed: one JSON line with the whole-run throughput in cell-updates/s, the
 roofline of the dominant kernel (algorithmic bytes over its mean launch time
-from HIP events recorded around every launch in the timed region), and the
-CPU oracle timed on this host on a bounded sample.
+from HIP events recorded around every launch in the timed region, with the
+counter-measured bytes of the same kernel when they were taken on the
+current sources), the CPU oracle timed on this host on a bounded sample, and
+the surrogate section: time to the 64^3 focal window of the learned
+surrogate (one graph replay) and of the solver's exact route (init + one
+step of dt = R0 + cut-out), measured here, and the held-out error of the
+committed training report.
 """
 import argparse
 import json

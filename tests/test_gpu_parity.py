@@ -80,7 +80,7 @@ def test_C1_pulse_f64_init_and_64_steps_match_oracle():
 
 SHAPES = [(8, 8, 8), (16, 24, 32), (8, 8, 1024), (8, 1024, 8), (1024, 8, 8), (24, 48, 96),
           (12 * 2, 16, 768), (16, 384, 8), (192, 8, 16), (64, 64, 64), (32, 128, 256), (16, 512, 16),
-          (512, 16, 8)]
+          (512, 16, 8), (16, 64, 32), (8, 256, 96)]     # the last two: 256-byte y strips
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=[f"{s[2]}x{s[1]}x{s[0]}" for s in SHAPES])

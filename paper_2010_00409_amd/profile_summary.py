@@ -13,14 +13,38 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 
 COPY_BYTES = 1 << 30
 
 
+def _gemm_args(name):
+    """Template arguments of a surrogate GEMM kernel name, demangled or not."""
+    if "k_gemm<" in name:
+        return name.split("k_gemm<", 1)[1].split(">(", 1)[0].replace(" ", "")
+    code = name.split("k_gemmI", 1)[1].split("EEvN", 1)[0] + "E"
+    words = {"f": "float", "d": "double", "DF16b": "bf16", "Lb0E": "false", "Lb1E": "true"}
+    out = []
+    while code and code != "E":
+        m = re.match(r"Li(-?\d+)E", code)
+        if m:
+            out.append(m.group(1))
+            code = code[m.end():]
+            continue
+        for k, v in words.items():
+            if code.startswith(k):
+                out.append(v)
+                code = code[len(k):]
+                break
+        else:
+            return name[:60]
+    return ",".join(out)
+
+
 def _short(name):
     if "k_gemm" in name:                      # surrogate GEMM: keep the tile shape and types
-        return "k_gemm<" + name.split("k_gemmI", 1)[-1].split("EEvNS", 1)[0] + ">"
+        return "k_gemm<" + _gemm_args(name) + ">"
     for key in ("k_z_fast", "k_col_fast", "k_x_forward", "k_x_inverse", "k_init_map", "k_readout",
                 "k_lift_x", "k_line_fwd", "k_line_proj", "k_lineout", "k_proj", "k_head_eff",
                 "k_col", "k_z", "k_sumsq", "k_reduce", "copy"):

@@ -25,7 +25,7 @@ struct StepParams {
     double cdt;              // c dt
     double scale;            // 1 / (nx ny nz)
     int project_b;           // also remove the longitudinal part of B
-    int zvariant;            // shape of the fused float32 z kernel (strip modes, elements per lane)
+    int zvariant;            // shape of the fused float32 z kernel (strip modes, elements per lane, first radix)
 };
 
 enum ZMode { Z_STEP = 0, Z_DIAG = 1 };

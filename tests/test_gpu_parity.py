@@ -186,6 +186,20 @@ def test_reversibility_and_semigroup_on_gpu_f32():
     assert rel(fwd.astype(np.float64), jump.astype(np.float64)) < 1e-5
 
 
+@pytest.mark.parametrize("zvariant", [3, 4])
+@pytest.mark.parametrize("dt", [1.0e4, -3.7e5])
+def test_f32_huge_dt_step_matches_oracle(dt, zvariant, monkeypatch):
+    """One float32 step with phases c |k| dt of 1e5-1e7 rad (Sec. II.A: the
+    vacuum step is exact for any dt) against the oracle's float64 step: the
+    float32 rotation's |k| and phase reduction must hold float64 accuracy."""
+    monkeypatch.setenv("TFOCUS_ZVARIANT", str(zvariant))
+    g, st = transverse_state(24, (64, 64, 64), 0.3)
+    st = st.astype(np.float32).astype(np.float64)
+    out, _ = run_gpu(g, "f32", st, 1, dt)
+    Eo, Bo = psatd.step_fft(st[:3], st[3:], spacing(g), dt)
+    assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= F32_TOL
+
+
 def test_determinism_bitwise():
     g, st = transverse_state(23, (64, 64, 64), 0.25)
     a, _ = run_gpu(g, "f32", st.astype(np.float32), 3, 0.4)
@@ -194,7 +208,7 @@ def test_determinism_bitwise():
 
 
 @pytest.mark.parametrize("n", [64, 128, 192])
-@pytest.mark.parametrize("zvariant", [0, 1, 2, 3])
+@pytest.mark.parametrize("zvariant", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("row_block", ["8", "n"])
 def test_every_kernel_plan_keeps_parity(n, zvariant, row_block, monkeypatch):
     """Each z strip shape and y row blocking the tuner can pick."""

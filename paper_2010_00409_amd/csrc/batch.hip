@@ -471,7 +471,7 @@ tf_status tf_tune(const int32_t* sizes, int32_t n, int32_t precision, const char
             p.row_block = rb;
             p.fast = false;
             cands.push_back(p);
-            for (int zv = 0; zv < 5; ++zv) {
+            for (int zv = 0; zv < 7; ++zv) {
                 p.fast = true;
                 p.zvariant = zv;
                 cands.push_back(p);

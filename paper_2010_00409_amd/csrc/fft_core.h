@@ -272,7 +272,10 @@ __device__ __forceinline__ void lg_stage_compute(C2<T> (&x)[E], C2<T>* reg, cons
     }
 }
 
-template <typename T, int N, int E, int DIR, int S, int S2, int TWN = N, int ST = 0, int NS = 1>
+// TAIL = false drops the barrier after the last exchange's reads: for callers
+// whose next LDS writes go to other regions, with a barrier between them and
+// the next writes to these.
+template <typename T, int N, int E, int DIR, int S, int S2, int TWN = N, int ST = 0, int NS = 1, bool TAIL = true>
 __device__ __forceinline__ void lg_fft2(C2<T> (&xa)[E], C2<T> (&xb)[E], C2<T>* rega, C2<T>* regb, const C2<T>* tw,
                                         int u) {
     if constexpr (ST < LGPlan<N, E>::nst) {
@@ -288,9 +291,9 @@ __device__ __forceinline__ void lg_fft2(C2<T> (&xa)[E], C2<T> (&xb)[E], C2<T>* r
                 xa[e] = rega[A::at(u + G * e)];
                 xb[e] = regb[A::at(u + G * e)];
             }
-            __syncthreads();
+            if constexpr (TAIL || ST + 2 < LGPlan<N, E>::nst) __syncthreads();
         }
-        lg_fft2<T, N, E, DIR, S, S2, TWN, ST + 1, NS * R>(xa, xb, rega, regb, tw, u);
+        lg_fft2<T, N, E, DIR, S, S2, TWN, ST + 1, NS * R, TAIL>(xa, xb, rega, regb, tw, u);
     }
 }
 

@@ -60,16 +60,11 @@ def traffic_record(kernel):
     path = os.path.join(HERE, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    import hashlib
     rec = json.load(open(path)).get(PASS_KERNEL.get(kernel, kernel))
     if not rec:
         return None
-    src = os.path.join(HERE, "paper_2010_00409_amd", "csrc")
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(src)):
-        if f.endswith((".hip", ".h", ".inc")):
-            h.update(open(os.path.join(src, f), "rb").read())
-    if rec.get("source_sha256") != h.hexdigest():
+    from paper_2010_00409_amd.profile_summary import source_hash
+    if rec.get("source_sha256") != source_hash():
         return None
     return rec.get("bytes_per_launch")
 

@@ -264,8 +264,11 @@ tf_status tf_set_plan_file(const char* path);
 /* For each cube size N in sizes[0..n): time a few steps of every kernel
  * plan (y row blocking 8 or none; generic kernels or the fast float32
  * kernels with each z strip shape) on the current device with HIP events,
- * keep the fastest, and merge "arch precision N N N row_block fast zvariant
- * ms" into plan_path.  best_ms (nullable) receives the best ms per step. */
+ * on pseudo-random fields, in three interleaved rounds (each plan keeps its
+ * fastest round); keep the fastest plan and merge "arch precision N N N
+ * row_block fast zvariant ms" into plan_path.  best_ms (nullable) receives
+ * the best ms per step.  Allocates two N^3 six-component states on the
+ * current device for the duration of the call. */
 tf_status tf_tune(const int32_t* sizes, int32_t n, int32_t precision, const char* plan_path, double* best_ms);
 
 /* ---- learned surrogate (Fourier neural operator) ----------------------- */

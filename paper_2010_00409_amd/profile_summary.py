@@ -105,12 +105,27 @@ def copy_value(d, counter):
     return sum(vals) / len(vals), rows[0][0]
 
 
-def source_hash():
+def kernel_sources(unit="fft_f32.hip"):
+    """The files the float32 pass kernels are compiled from: the translation
+    unit and the csrc headers it includes, transitively, in include order."""
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    order, todo = [], [unit]
+    while todo:
+        f = todo.pop(0)
+        path = os.path.join(src, f)
+        if f in order or not os.path.exists(path):
+            continue
+        order.append(f)
+        todo += re.findall(r'^#include "([^"/]+)"', open(path).read(), re.M)
+    return [os.path.join(src, f) for f in order]
+
+
+def source_hash():
+    """SHA-256 of the pass kernels' sources: counters recorded against it
+    stay valid while those kernels are unchanged."""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(src)):
-        if f.endswith((".hip", ".h", ".inc")):
-            h.update(open(os.path.join(src, f), "rb").read())
+    for path in kernel_sources():
+        h.update(open(path, "rb").read())
     return h.hexdigest()
 
 

@@ -197,7 +197,23 @@ template <int N, int S, int S2> struct LgAt {
     static constexpr int span = (N - 1) * S + ((N - 1) >> PSH) * PAD + 1;
 };
 
-template <typename T, int N, int E, int R, int NS, int DIR, int S, int S2, int TWN>
+// Orders one wave's LDS writes before its later LDS reads (a wave's LDS
+// operations complete in issue order; the fences keep the compiler from
+// moving memory operations across the point).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Barrier of a lane group's exchange: the whole block, or only the wave when
+// every lane group lies inside one wave (WAVE).
+template <bool WAVE> __device__ __forceinline__ void lg_sync() {
+    if constexpr (WAVE) wave_sync();
+    else __syncthreads();
+}
+
+template <typename T, int N, int E, int R, int NS, int DIR, int S, int S2, int TWN, bool WAVE = false>
 __device__ __forceinline__ void lg_stage_tw(C2<T> (&x)[E], C2<T>* reg, const C2<T>* tw, int u) {
     constexpr int G = N / E, Q = E / R;
     constexpr bool LAST = (NS * R == N);
@@ -229,10 +245,10 @@ __device__ __forceinline__ void lg_stage_tw(C2<T> (&x)[E], C2<T>* reg, const C2<
         }
     }
     if constexpr (!LAST) {
-        __syncthreads();
+        lg_sync<WAVE>();
 #pragma unroll
         for (int e = 0; e < E; ++e) x[e] = reg[A::at(u + G * e)];
-        __syncthreads();
+        lg_sync<WAVE>();
     }
 }
 
@@ -298,12 +314,17 @@ __device__ __forceinline__ void lg_fft2(C2<T> (&xa)[E], C2<T> (&xb)[E], C2<T>* r
 }
 
 // tw: table of TWN entries exp(-2 pi i e / TWN), TWN a multiple of N.
-template <typename T, int N, int E, int DIR, int S, int S2, int TWN = N, int ST = 0, int NS = 1>
+// WAVE: every lane group lies inside one wave (N / E divides 64 and groups
+// start at multiples of N / E), so exchanges only order the wave's own LDS
+// accesses; the caller still synchronises the block around the transform
+// wherever other lane groups touch this group's region.
+template <typename T, int N, int E, int DIR, int S, int S2, int TWN = N, int ST = 0, int NS = 1, bool WAVE = false>
 __device__ __forceinline__ void lg_fft(C2<T> (&x)[E], C2<T>* reg, const C2<T>* tw, int u) {
+    static_assert(!WAVE || 64 % (N / E) == 0, "a wave-synchronised lane group must fit in one wave");
     if constexpr (ST < LGPlan<N, E>::nst) {
         constexpr int R = LGPlan<N, E>::radix(ST);
-        lg_stage_tw<T, N, E, R, NS, DIR, S, S2, TWN>(x, reg, tw, u);
-        lg_fft<T, N, E, DIR, S, S2, TWN, ST + 1, NS * R>(x, reg, tw, u);
+        lg_stage_tw<T, N, E, R, NS, DIR, S, S2, TWN, WAVE>(x, reg, tw, u);
+        lg_fft<T, N, E, DIR, S, S2, TWN, ST + 1, NS * R, WAVE>(x, reg, tw, u);
     }
 }
 

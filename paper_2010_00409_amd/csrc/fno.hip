@@ -881,18 +881,25 @@ __global__ __launch_bounds__(256) void k_loss_part(const float* out, const float
     }
 }
 
-// res[0] = loss; res[1 + b] = dL/dout scale 1 / (B ||d_b|| ||y_b||)
-__global__ void k_loss_final(const double* part, int nch, int B, double* res) {
-    if (threadIdx.x != 0) return;
-    double L = 0;
-    for (int b = 0; b < B; ++b) {
+// res[0] = loss; res[1 + b] = dL/dout scale 1 / (B ||d_b|| ||y_b||).  One
+// thread per sample (strided over the block); the loss sums the samples in
+// order b = 0..B-1.  Launched with one block of LOSS_THREADS threads.
+constexpr int LOSS_THREADS = 256;
+__global__ __launch_bounds__(LOSS_THREADS) void k_loss_final(const double* part, int nch, int B, double* res,
+                                                             double* ratio) {
+    for (int b = threadIdx.x; b < B; b += LOSS_THREADS) {
         double sd = 0, sy = 0;
         for (int k = 0; k < nch; ++k) { sd += part[(b * nch + k) * 2]; sy += part[(b * nch + k) * 2 + 1]; }
         const double nd = sqrt(sd), ny = sqrt(sy);
-        L += nd / ny;
+        ratio[b] = nd / ny;
         res[1 + b] = nd > 0 ? 1.0 / (double(B) * nd * ny) : 0.0;
     }
-    res[0] = L / B;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double L = 0;
+        for (int b = 0; b < B; ++b) L += ratio[b];
+        res[0] = L / B;
+    }
 }
 
 __global__ void k_gout(const float* out, const float* y, const double* res, float* g, int64_t total) {
@@ -902,14 +909,31 @@ __global__ void k_gout(const float* out, const float* y, const double* res, floa
     g[i] = float(double(out[i] - y[i]) * res[1 + b]);
 }
 
-// dst[y][e] = sum_p part[y][p][e] (y = blockIdx.y), in a fixed order
-__global__ void k_reduce(const float* part, int nparts, int len, float* dst) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= len) return;
+// dst[y][e] = sum_p part[y][p][e] (y = blockIdx.y), in a fixed order: a
+// block takes 64 consecutive e; lane q = threadIdx.x / 64 of column e sums
+// the partials p = q (mod 4) in increasing p, eight loads in flight, and
+// the four lane sums are added in order q = 0..3.
+__global__ __launch_bounds__(256) void k_reduce(const float* part, int nparts, int len, float* dst) {
+    const int el = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + el;
     const float* src = part + int64_t(blockIdx.y) * nparts * len;
     float s = 0;
-    for (int p = 0; p < nparts; ++p) s += src[int64_t(p) * len + e];
-    dst[int64_t(blockIdx.y) * len + e] = s;
+    if (e < len) {
+        int p = q;
+        for (; p + 28 < nparts; p += 32) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = src[int64_t(p + 4 * k) * len + e];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s += v[k];
+        }
+        for (; p < nparts; p += 4) s += src[int64_t(p) * len + e];
+    }
+    __shared__ float red[4][64];
+    red[q][el] = s;
+    __syncthreads();
+    if (q == 0 && e < len)
+        dst[int64_t(blockIdx.y) * len + e] = ((red[0][el] + red[1][el]) + red[2][el]) + red[3][el];
 }
 
 // dL/dR from the real 64x64 block gradient G* of Y* = X* R*:
@@ -1351,7 +1375,7 @@ tf_status tf_fno_create(int32_t max_batch, int32_t training, int32_t nbasis, voi
     TRY(f->alloc(&f->X3[0], B * X3_SZ));
     TRY(f->alloc(&f->Y, B * X3_SZ));
     TRY(f->alloc(&f->out, B * OUT_SZ));
-    TRY(f->alloc(&f->dres, 1 + B));
+    TRY(f->alloc(&f->dres, 1 + 2 * B));      // loss, per-sample scales, per-sample ratios
     TRY(f->alloc(&f->lpart, B * LOSS_CH * 2));
     if (f->training) {
         TRY(f->alloc(&f->grad, NPARAMS));
@@ -1485,7 +1509,7 @@ tf_status forward(tf_fno* f, const float* params, const float* hw, int B, float*
 
 // split-K weight gradient [A | 1]^T-style reductions into the flat gradient
 tf_status reduce_into(tf_fno* f, int nparts, int len, float* dst, int groups = 1) {
-    hipLaunchKernelGGL(k_reduce, dim3((len + 255) / 256, groups), dim3(256), 0, f->cur, f->part, nparts, len, dst);
+    hipLaunchKernelGGL(k_reduce, dim3((len + 63) / 64, groups), dim3(256), 0, f->cur, f->part, nparts, len, dst);
     return launched();
 }
 
@@ -1495,7 +1519,8 @@ tf_status backward(tf_fno* f, const float* params, const float* hw, const float*
     const int64_t szO = nb * OUT_SZ, szH = nb * HID * N3, szP = nb * NCHUNK * 33 * HID;
     // loss and dL/dout
     hipLaunchKernelGGL(k_loss_part, dim3(LOSS_CH, B), dim3(256), 0, f->cur, f->out, target, f->lpart);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, f->cur, f->lpart, LOSS_CH, B, f->dres);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(LOSS_THREADS), 0, f->cur, f->lpart, LOSS_CH, B, f->dres,
+                       f->dres + 1 + B);
     hipLaunchKernelGGL(k_gout, dim3((szO + 255) / 256), dim3(256), 0, f->cur, f->out, target, f->dres, f->gout, szO);
     TRY(launched());
     // projection

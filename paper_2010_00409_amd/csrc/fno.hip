@@ -837,23 +837,36 @@ __global__ __launch_bounds__(256) void k_lift_grad_part(const float* gv, float* 
 }
 
 // dL/dW0, dL/db0 from the per-plane sums (one thread per channel)
-__global__ void k_lift_grad_final(const float* part, const float* p, int B, float* grad) {
-    const int c = threadIdx.x;
-    if (c >= C) return;
-    float gw[11] = {0};
-    float gb = 0;
-    for (int b = 0; b < B; ++b) {
+// One block of LIFT_THREADS: thread (bq, c) takes the samples b = bq (mod
+// 32) in increasing b; the 32 lane sums of each of the 12 outputs are then
+// added in order bq = 0..31.
+constexpr int LIFT_THREADS = 1024;
+__global__ __launch_bounds__(LIFT_THREADS) void k_lift_grad_final(const float* part, const float* p, int B,
+                                                                  float* grad) {
+    constexpr int NQ = LIFT_THREADS / C, NV = 12;
+    const int c = threadIdx.x % C, bq = threadIdx.x / C;
+    float gw[NV] = {0};                       // 8 parameter weights, 3 coordinate weights, bias
+    for (int b = bq; b < B; b += NQ) {
         float s = 0, sx = 0, sy = 0, sz = 0;
+#pragma unroll 8
         for (int z = 0; z < N; ++z) {
             const float* o = part + (int64_t(b) * N + z) * 4 * C;
             s += o[c]; sx += o[C + c]; sy += o[2 * C + c]; sz += o[3 * C + c];
         }
         for (int i = 0; i < NPAR; ++i) gw[i] += p[b * NPAR + i] * s;
         gw[8] += sx; gw[9] += sy; gw[10] += sz;
-        gb += s;
+        gw[11] += s;
     }
-    for (int i = 0; i < 11; ++i) grad[OFF_W0 + i * C + c] = gw[i];
-    grad[OFF_B0 + c] = gb;
+    __shared__ float red[NQ][NV][C];
+    for (int i = 0; i < NV; ++i) red[bq][i][c] = gw[i];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NV * C; idx += LIFT_THREADS) {
+        const int i = idx / C, cc = idx % C;
+        float t = 0;
+        for (int q = 0; q < NQ; ++q) t += red[q][i][cc];
+        if (i < 11) grad[OFF_W0 + i * C + cc] = t;
+        else grad[OFF_B0 + cc] = t;
+    }
 }
 
 // per (chunk, sample): sum (out - y)^2 and sum y^2 in float64
@@ -1071,9 +1084,11 @@ inline Operand opnd(const void* p, Ix r, Ix c, int64_t b1, int64_t b2, int fast_
 }
 
 // Whether groups of 4 along the operand's contiguous index are contiguous and
-// aligned for 4-element loads (rows x cols is the operand's shape).
+// aligned for 4-element loads (rows x cols is the operand's shape).  Rows
+// from ones_from on are never loaded (stage takes them first), so they do
+// not bar the vector loads of the others.
 inline bool vec_ok(const Operand& o, int rows, int cols, bool is_b, size_t elem) {
-    if (!o.p || o.ones_from < (1 << 30) || !o.fast_k) return false;
+    if (!o.p || !o.fast_k) return false;
     const bool k_is_row = is_b;                 // A: (M, K); B: (K, N)
     const Ix fast = o.fast_k ? (k_is_row ? o.r : o.c) : (k_is_row ? o.c : o.r);
     const Ix slow = o.fast_k ? (k_is_row ? o.c : o.r) : (k_is_row ? o.r : o.c);
@@ -1578,7 +1593,7 @@ tf_status backward(tf_fno* f, const float* params, const float* hw, const float*
         g = gn;
     }
     hipLaunchKernelGGL(k_lift_grad_part, dim3(N, B), dim3(256), 0, f->cur, g, f->part);
-    hipLaunchKernelGGL(k_lift_grad_final, dim3(1), dim3(64), 0, f->cur, f->part, params, B, f->grad);
+    hipLaunchKernelGGL(k_lift_grad_final, dim3(1), dim3(LIFT_THREADS), 0, f->cur, f->part, params, B, f->grad);
     return launched();
 }
 

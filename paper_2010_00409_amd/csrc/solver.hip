@@ -51,6 +51,11 @@ struct tf_solver {
     bool prof = false;
     std::vector<hipEvent_t> evpool;
     std::vector<int> rec_kind;
+    // GRAPH_STEPS steps of one dt, captured once on a private stream and
+    // replayed on `stream` by tf_advance
+    hipStream_t cap = nullptr;
+    hipGraphExec_t step_exec = nullptr;
+    double step_dt = 0.0;
 };
 
 namespace {
@@ -109,7 +114,47 @@ hipError_t one_step(tf_solver* s, double dt, bool project_b) {
     });
 }
 
+// Steps per captured graph: the launch cost of the remaining steps is one
+// graph launch per GRAPH_STEPS steps.
+constexpr int64_t GRAPH_STEPS = 8;
+
+// The graph of GRAPH_STEPS steps of dt (without the B projection), captured
+// on first use and again whenever dt changes.
+template <typename T>
+tf_status step_graph(tf_solver* s, double dt) {
+    if (s->step_exec && std::memcmp(&s->step_dt, &dt, sizeof dt) == 0) return TF_OK;
+    if (!s->cap) TF_HIP(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
+    if (s->step_exec) {
+        TF_HIP(hipGraphExecDestroy(s->step_exec));
+        s->step_exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    TF_HIP(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+    hipStream_t user = s->stream;
+    s->stream = s->cap;                       // the pass launchers enqueue on s->stream
+    hipError_t e = hipSuccess;
+    for (int64_t k = 0; k < GRAPH_STEPS && e == hipSuccess; ++k) e = one_step<T>(s, dt, false);
+    s->stream = user;
+    hipError_t e2 = hipStreamEndCapture(s->cap, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(TF_EDEVICE, std::string("step graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&s->step_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        s->step_exec = nullptr;
+        return fail(TF_EDEVICE, std::string("step graph instantiate: ") + hipGetErrorString(e));
+    }
+    s->step_dt = dt;
+    return TF_OK;
+}
+
 void free_all(tf_solver* s) {
+    if (s->step_exec) (void)hipGraphExecDestroy(s->step_exec);
+    if (s->cap) (void)hipStreamDestroy(s->cap);
+    s->step_exec = nullptr;
+    s->cap = nullptr;
     for (hipEvent_t ev : s->evpool) (void)hipEventDestroy(ev);
     s->evpool.clear();
     void* ptrs[] = {s->state, s->spec, s->tw[0], s->tw[1], s->tw[2], s->partials, s->results,
@@ -316,11 +361,29 @@ tf_status tf_advance(tf_solver* s, int64_t nsteps, double dt) {
     if (!s) return fail(TF_EINVAL, "solver is NULL");
     if (nsteps < 0) return fail(TF_EINVAL, "nsteps must be >= 0");
     if (!std::isfinite(dt)) return fail(TF_EINVAL, "dt must be finite");
-    for (int64_t i = 0; i < nsteps; ++i) {
-        const bool pb = s->project_b_next;
+    auto eager = [&](bool pb) -> tf_status {
         hipError_t e = s->prec == TF_F64 ? one_step<double>(s, dt, pb) : one_step<float>(s, dt, pb);
         if (e != hipSuccess) return fail(TF_EDEVICE, std::string("step: ") + hipGetErrorString(e));
+        return TF_OK;
+    };
+    int64_t i = 0;
+    if (s->project_b_next && nsteps > 0) {    // the first step after new fields also removes longitudinal B
+        tf_status st = eager(true);
+        if (st != TF_OK) return st;
         s->project_b_next = false;
+        i = 1;
+    }
+    // whole graphs of GRAPH_STEPS steps, unless every launch is being timed
+    const int64_t graphs = s->prof ? 0 : (nsteps - i) / GRAPH_STEPS;
+    if (graphs > 0) {
+        tf_status st = s->prec == TF_F64 ? step_graph<double>(s, dt) : step_graph<float>(s, dt);
+        if (st != TF_OK) return st;
+        for (int64_t r = 0; r < graphs; ++r) TF_HIP(hipGraphLaunch(s->step_exec, s->stream));
+        i += graphs * GRAPH_STEPS;
+    }
+    for (; i < nsteps; ++i) {
+        tf_status st = eager(false);
+        if (st != TF_OK) return st;
     }
     s->t = s->t + (double)nsteps * dt;
     return TF_OK;

@@ -200,6 +200,35 @@ def test_f32_huge_dt_step_matches_oracle(dt, zvariant, monkeypatch):
     assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= F32_TOL
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_graph_replayed_steps_equal_eager_steps_bitwise(prec):
+    """tf_advance replays a captured graph of 8 steps and runs the remainder
+    (and, after tf_set_pulse, the first step with the B projection) eagerly;
+    with per-launch profiling every step is launched eagerly.  Both must give
+    the same bits, across a re-capture for a new dt and a cached replay."""
+    dtype = np.float64 if prec == "f64" else np.float32
+    g, st = transverse_state(25, (32, 48, 64), 0.3)
+    st = np.ascontiguousarray(st.astype(dtype))
+    plan = [(21, 0.37), (16, -0.21), (9, 0.37), (3, 0.37)]
+    outs = []
+    for eager in (True, False):
+        with tf.Solver(g, prec) as s:
+            s.set_fields(st, 0.5)
+            s.profile(eager)
+            for n, dt in plan:
+                s.advance(n, dt)
+            out = np.empty(s.shape, dtype=dtype)
+            s.get_fields(out)
+            outs.append((out, s.t))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1] == 0.5 + 21 * 0.37 + 16 * -0.21 + 9 * 0.37 + 3 * 0.37
+    Eo, Bo = psatd.step_fft(st[:3].astype(np.float64), st[3:].astype(np.float64), spacing(g), 0.37, nsteps=21)
+    Eo, Bo = psatd.step_fft(Eo, Bo, spacing(g), -0.21, nsteps=16)
+    Eo, Bo = psatd.step_fft(Eo, Bo, spacing(g), 0.37, nsteps=12)
+    tol = 1e-11 if prec == "f64" else 2 * F32_TOL
+    assert rel(outs[1][0].astype(np.float64), np.concatenate([Eo, Bo])) <= tol
+
+
 def test_determinism_bitwise():
     g, st = transverse_state(23, (64, 64, 64), 0.25)
     a, _ = run_gpu(g, "f32", st.astype(np.float32), 3, 0.4)

@@ -229,6 +229,19 @@ def test_graph_replayed_steps_equal_eager_steps_bitwise(prec):
     assert rel(outs[1][0].astype(np.float64), np.concatenate([Eo, Bo])) <= tol
 
 
+@pytest.mark.parametrize("zvariant", [0, 1, 2, 3, 4, 5, 6])
+def test_every_z_variant_at_length_512(zvariant, monkeypatch):
+    """512-point z columns (where variants 5 and 6 differ, and residues are
+    parked in LDS or held in registers) on a thin grid, two steps against
+    the oracle."""
+    monkeypatch.setenv("TFOCUS_ZVARIANT", str(zvariant))
+    g, st = transverse_state(40 + zvariant, (512, 8, 16), 0.3)
+    st = st.astype(np.float32).astype(np.float64)
+    out, _ = run_gpu(g, "f32", st, 2, 0.41)
+    Eo, Bo = psatd.step_fft(st[:3], st[3:], spacing(g), 0.41, nsteps=2)
+    assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= 2 * F32_TOL
+
+
 def test_determinism_bitwise():
     g, st = transverse_state(23, (64, 64, 64), 0.25)
     a, _ = run_gpu(g, "f32", st.astype(np.float32), 3, 0.4)

@@ -188,7 +188,11 @@ tf_status tf_set_cutout(tf_solver* s, double R_min, double R_max);
  * per-mode rotation of Eqs. (3)-(4) with C = cos(c|k|dt), S = sin(c|k|dt),
  * inverse FFT.  k-space conventions: forward transform exp(-i k.x); k_hat =
  * 0 at k = 0; Nyquist indices contribute 0 to k.  t += nsteps * dt.
- * Asynchronous on the solver's stream. */
+ * Asynchronous on the solver's stream.  Runs of eight steps are replayed
+ * from a graph captured on a private stream at the first such call with
+ * this dt (and again when dt changes), owned by the solver; the first step
+ * after tf_set_pulse, the remainder and all steps while tf_profile is on
+ * are launched directly.  Both give the same bits. */
 tf_status tf_advance(tf_solver* s, int64_t nsteps, double dt);
 
 /* Focal window [6][wz][wy][wx] at the current time: u(R) = u~(T(R)) I_S(t)(R),

@@ -153,8 +153,10 @@ tf_status tf_layer_grid(const tf_pulse* pulse, int32_t nx, int32_t ny, int32_t n
 /* Create a solver on the current HIP device.  Allocates the field state
  * (6 nx ny nz elements) and the half spectrum (6 nz ny nkx complex, nkx =
  * nx/2 + 1 rounded up to 4).  The state starts at zero with t = 0.
- * hip_stream: hipStream_t or NULL.  TF_ENOMEM if the environment variable
- * TFOCUS_MAX_DEVICE_BYTES is set below the bytes needed. */
+ * hip_stream: hipStream_t or NULL (a stream of that device).  Every later
+ * call on the solver must be made with the same device current.  TF_ENOMEM
+ * if the environment variable TFOCUS_MAX_DEVICE_BYTES is set below the
+ * bytes needed. */
 tf_status tf_create(const tf_grid* grid, int32_t precision, void* hip_stream,
                     tf_solver** out);
 
@@ -239,7 +241,8 @@ typedef struct tf_batch tf_batch;
  * identical grids share one allocation and run together: every pass of a
  * step is one launch over all active instances of that grid.  Validates
  * every grid and pulse (TF_EDOMAIN if an instance's D <= L) and uploads the
- * pulse tables; the states are initialised by tf_batch_run. */
+ * pulse tables; the states are initialised by tf_batch_run.  Lives on the
+ * current HIP device; later calls need the same device current. */
 tf_status tf_batch_create(const tf_grid* grids, const tf_pulse* pulses, int32_t n, int32_t precision,
                           void* hip_stream, tf_batch** out);
 

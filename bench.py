@@ -90,7 +90,7 @@ def cpu_baseline(n, seed=3):
 # surrogate training report whose held-out error the bench quotes (written by
 # python -m paper_2010_00409_amd.surrogate on MI355X; the weights themselves
 # are not kept, and inference time does not depend on their values)
-SURROGATE_REPORTS = ("surrogate_k4_head_4000x320_batch8.json", "surrogate_k4_head_4000x400.json", "surrogate_k4_head_4000x340.json", "surrogate_k4_head_4000x200.json",
+SURROGATE_REPORTS = ("surrogate_k4_head_4000x230_batch4.json", "surrogate_k4_head_4000x320_batch8.json", "surrogate_k4_head_4000x400.json", "surrogate_k4_head_4000x340.json", "surrogate_k4_head_4000x200.json",
                      "surrogate_k4_head_4000x140.json", "surrogate_k4_head_4000x60.json")
 
 

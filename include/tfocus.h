@@ -152,7 +152,8 @@ tf_status tf_layer_grid(const tf_pulse* pulse, int32_t nx, int32_t ny, int32_t n
 
 /* Create a solver on the current HIP device.  Allocates the field state
  * (6 nx ny nz elements) and the half spectrum (6 nz ny nkx complex, nkx =
- * nx/2 + 1 rounded up to 4).  The state starts at zero with t = 0.
+ * nx/2: the x DC and Nyquist planes share slot 0 as F(0) + i F(nx/2)), so
+ * about 12 nx ny nz elements in all.  The state starts at zero with t = 0.
  * hip_stream: hipStream_t or NULL (a stream of that device).  Every later
  * call on the solver must be made with the same device current.  TF_ENOMEM
  * if the environment variable TFOCUS_MAX_DEVICE_BYTES is set below the
@@ -252,8 +253,10 @@ tf_status tf_batch_create(const tf_grid* grids, const tf_pulse* pulses, int32_t 
  * (shared shape and centre, Eqs. (14)-(16) at t_i = nsteps[i] dt[i]) into
  * dst_dev + i * 6 * wx * wy * wz (device memory, n windows, solver element
  * type).  use_graph = 1 captures the whole sweep into a hipGraph on first
- * use and replays it while nsteps, dt, the window and dst_dev are unchanged;
- * 0 launches eagerly.  Asynchronous on the batch stream. */
+ * use and replays it while nsteps, dt, the window and dst_dev are unchanged
+ * and no other run came between; 0 launches eagerly (and drops a captured
+ * graph, whose slot order it may change).  Asynchronous on the batch
+ * stream. */
 tf_status tf_batch_run(tf_batch* b, const int64_t* nsteps, const double* dt, const tf_window* win,
                        void* dst_dev, int32_t use_graph);
 
@@ -267,6 +270,16 @@ tf_status tf_batch_destroy(tf_batch* b);
 /* Plan file consulted by tf_create and tf_batch_create (also taken from the
  * environment variable TFOCUS_PLAN_FILE).  NULL or "" clears it. */
 tf_status tf_set_plan_file(const char* path);
+
+/* Host only.  The kernel plan tf_create and tf_batch_create use for a grid:
+ * the y row blocking of the spectrum, whether the fast float32 kernels may
+ * run (0 selects the generic kernels; also 0 when the fast z kernel's 32-bit
+ * strip offsets would not reach a row of the spectrum), and the fast z
+ * kernel's strip shape.  From the plan file, then the environment overrides
+ * TFOCUS_ROW_BLOCK, TFOCUS_GENERIC_KERNELS and TFOCUS_ZVARIANT.  Any output
+ * pointer may be NULL. */
+tf_status tf_kernel_plan(const tf_grid* grid, int32_t precision, int32_t* row_block, int32_t* fast,
+                         int32_t* zvariant);
 
 /* For each cube size N in sizes[0..n): time a few steps of every kernel
  * plan (y row blocking 8 or none; generic kernels or the fast float32

@@ -104,6 +104,9 @@ tf::host::KernelPlan tf::host::plan_for(const tf_grid& g, int precision) {
         }
     }
     env_overrides(g, p);
+    // a plan (file line or environment) whose strip offsets would not fit
+    // 32 bits runs the generic kernels, which address with 64 bits
+    if (p.fast && !fast_offsets_fit(g, p.row_block, precision)) p.fast = false;
     return p;
 }
 
@@ -246,6 +249,25 @@ __global__ void k_tune_fill(T* p, size_t n) {
     }
 }
 
+// Device buffers and events of one tuning size, released on every return
+// path (the device is synchronised first, so no queued work still uses them).
+struct TuneBuffers {
+    void* state = nullptr;
+    void* spec = nullptr;
+    void* tw[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TuneBuffers() = default;
+    TuneBuffers(const TuneBuffers&) = delete;
+    TuneBuffers& operator=(const TuneBuffers&) = delete;
+    ~TuneBuffers() {
+        (void)hipDeviceSynchronize();
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        for (void* p : {state, spec, tw[0], tw[1], tw[2]})
+            if (p) (void)hipFree(p);
+    }
+};
+
 }  // namespace
 
 extern "C" {
@@ -377,6 +399,16 @@ tf_status tf_batch_run(tf_batch* b, const int64_t* nsteps, const double* dt, con
                         std::equal(nsteps, nsteps + b->n, b->key_steps.begin()) &&
                         std::equal(dt, dt + b->n, b->key_dt.begin()) && !std::memcmp(&b->key_win, w, sizeof(*w));
     if (!cached) {
+        // the slot order and the per-slot dt below are what a captured graph
+        // reads: once they are rewritten, no earlier graph may be replayed
+        if (b->exec) {
+            TF_HIP(hipStreamSynchronize(b->stream));
+            TF_HIP(hipGraphExecDestroy(b->exec));
+            b->exec = nullptr;
+        }
+        b->key_steps.clear();
+        b->key_dt.clear();
+        b->key_dst = nullptr;
         // slot order: longest run first, so the active slots of a step are a prefix
         for (Group& G : b->groups) {
             G.slot_of = G.members;
@@ -394,10 +426,6 @@ tf_status tf_batch_run(tf_batch* b, const int64_t* nsteps, const double* dt, con
         return TF_OK;
     }
     if (!cached) {
-        if (b->exec) {
-            TF_HIP(hipGraphExecDestroy(b->exec));
-            b->exec = nullptr;
-        }
         hipGraph_t graph = nullptr;
         TF_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
         hipError_t e = enqueue_run(b, b->cap, nsteps, dt, *w, dst_dev);
@@ -446,6 +474,18 @@ tf_status tf_batch_destroy(tf_batch* b) {
     return TF_OK;
 }
 
+tf_status tf_kernel_plan(const tf_grid* grid, int32_t precision, int32_t* row_block, int32_t* fast,
+                         int32_t* zvariant) {
+    if (precision != TF_F32 && precision != TF_F64) return fail(TF_EINVAL, "precision must be TF_F32 or TF_F64");
+    tf_status st = validate_grid(grid);
+    if (st != TF_OK) return st;
+    const KernelPlan p = plan_for(*grid, precision);
+    if (row_block) *row_block = p.row_block;
+    if (fast) *fast = p.fast ? 1 : 0;
+    if (zvariant) *zvariant = p.zvariant;
+    return TF_OK;
+}
+
 tf_status tf_set_plan_file(const char* path) {
     std::lock_guard<std::mutex> lk(g_plan_mu);
     g_plan_path = path ? path : "";
@@ -471,15 +511,15 @@ tf_status tf_tune(const int32_t* sizes, int32_t n, int32_t precision, const char
         g.nx = g.ny = g.nz = N;
         g.dx = g.dy = g.dz = 1.0;
         const size_t cells = (size_t)N * N * N;
-        void *state = nullptr, *spec = nullptr, *tw[3] = {nullptr, nullptr, nullptr};
-        TF_HIP(hipMalloc(&state, 6 * cells * es));
-        TF_HIP(hipMalloc(&spec, 6 * cells * es));
+        TuneBuffers tb;
+        TF_HIP(hipMalloc(&tb.state, 6 * cells * es));
+        TF_HIP(hipMalloc(&tb.spec, 6 * cells * es));
         for (int a = 0; a < 3; ++a) {
-            TF_HIP(hipMalloc(&tw[a], 2 * es * N));
-            TF_HIP(upload_twiddles(tw[a], N, precision, nullptr));
+            TF_HIP(hipMalloc(&tb.tw[a], 2 * es * N));
+            TF_HIP(upload_twiddles(tb.tw[a], N, precision, nullptr));
         }
-        if (precision == TF_F64) hipLaunchKernelGGL(k_tune_fill<double>, dim3(1024), dim3(256), 0, nullptr, (double*)state, 6 * cells);
-        else hipLaunchKernelGGL(k_tune_fill<float>, dim3(1024), dim3(256), 0, nullptr, (float*)state, 6 * cells);
+        if (precision == TF_F64) hipLaunchKernelGGL(k_tune_fill<double>, dim3(1024), dim3(256), 0, nullptr, (double*)tb.state, 6 * cells);
+        else hipLaunchKernelGGL(k_tune_fill<float>, dim3(1024), dim3(256), 0, nullptr, (float*)tb.state, 6 * cells);
         TF_HIP(hipGetLastError());
         std::vector<KernelPlan> cands;
         for (int rb : {8, N}) {
@@ -487,15 +527,15 @@ tf_status tf_tune(const int32_t* sizes, int32_t n, int32_t precision, const char
             p.row_block = rb;
             p.fast = false;
             cands.push_back(p);
+            if (!fast_offsets_fit(g, rb, precision)) continue;
             for (int zv = 0; zv < 7; ++zv) {
                 p.fast = true;
                 p.zvariant = zv;
                 cands.push_back(p);
             }
         }
-        hipEvent_t e0, e1;
-        TF_HIP(hipEventCreate(&e0));
-        TF_HIP(hipEventCreate(&e1));
+        TF_HIP(hipEventCreate(&tb.e0));
+        TF_HIP(hipEventCreate(&tb.e1));
         KernelPlan best;
         double bms = 1e300;
         const int reps = N >= 256 ? 4 : 10;
@@ -510,18 +550,18 @@ tf_status tf_tune(const int32_t* sizes, int32_t n, int32_t precision, const char
                 hipError_t e = hipSuccess;
                 for (int r = 0; r < 2 && e == hipSuccess; ++r)
                     e = precision == TF_F64
-                            ? step_passes<double>(state, spec, tw, g, rm, p, 0.1, false, tf::Batch{}, nullptr)
-                            : step_passes<float>(state, spec, tw, g, rm, p, 0.1, false, tf::Batch{}, nullptr);
-                TF_HIP(hipEventRecord(e0, nullptr));
+                            ? step_passes<double>(tb.state, tb.spec, tb.tw, g, rm, p, 0.1, false, tf::Batch{}, nullptr)
+                            : step_passes<float>(tb.state, tb.spec, tb.tw, g, rm, p, 0.1, false, tf::Batch{}, nullptr);
+                TF_HIP(hipEventRecord(tb.e0, nullptr));
                 for (int r = 0; r < reps && e == hipSuccess; ++r)
                     e = precision == TF_F64
-                            ? step_passes<double>(state, spec, tw, g, rm, p, 0.1, false, tf::Batch{}, nullptr)
-                            : step_passes<float>(state, spec, tw, g, rm, p, 0.1, false, tf::Batch{}, nullptr);
-                TF_HIP(hipEventRecord(e1, nullptr));
-                TF_HIP(hipEventSynchronize(e1));
+                            ? step_passes<double>(tb.state, tb.spec, tb.tw, g, rm, p, 0.1, false, tf::Batch{}, nullptr)
+                            : step_passes<float>(tb.state, tb.spec, tb.tw, g, rm, p, 0.1, false, tf::Batch{}, nullptr);
+                TF_HIP(hipEventRecord(tb.e1, nullptr));
+                TF_HIP(hipEventSynchronize(tb.e1));
                 if (e != hipSuccess) return fail(TF_EDEVICE, std::string("tuning step: ") + hipGetErrorString(e));
                 float ms = 0.0f;
-                TF_HIP(hipEventElapsedTime(&ms, e0, e1));
+                TF_HIP(hipEventElapsedTime(&ms, tb.e0, tb.e1));
                 tmin[ci] = std::min(tmin[ci], double(ms) / reps);
             }
         for (size_t ci = 0; ci < cands.size(); ++ci)
@@ -529,11 +569,6 @@ tf_status tf_tune(const int32_t* sizes, int32_t n, int32_t precision, const char
                 bms = tmin[ci];
                 best = cands[ci];
             }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        (void)hipFree(state);
-        (void)hipFree(spec);
-        for (void* t : tw) (void)hipFree(t);
         found[PlanKey{arch, precision, N, N, N}] = {best, bms};
         if (best_ms) best_ms[i] = bms;
     }

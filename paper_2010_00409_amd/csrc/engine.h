@@ -274,6 +274,13 @@ struct KernelPlan {
 };
 KernelPlan plan_for(const tf_grid& g, int precision);
 
+// Whether the fast float32 kernels can address a grid with this row blocking
+// (the fast z kernel's 32-bit strip offsets, z_fast_offsets_fit).
+inline bool fast_offsets_fit(const tf_grid& g, int row_block, int precision) {
+    const size_t cb = precision == TF_F64 ? 16 : 8;
+    return z_fast_offsets_fit(g.nx, g.nz, row_block, cb);
+}
+
 // Pass sequence of one step on a set of same-shape instances.
 template <typename T>
 hipError_t step_passes(void* state, void* spec, void* const* tw, const tf_grid& g, const RowMap& rm,

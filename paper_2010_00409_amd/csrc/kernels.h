@@ -12,6 +12,14 @@ namespace tf {
 // a block are adjacent.
 inline int nkx_of(int nx) { return nx / 2; }
 
+// The fast z kernel addresses a strip as a block-uniform 64-bit base plus
+// 32-bit byte offsets; they reach (nz - 1) G rows of 6 nkx complex values
+// beyond the base (plus one row), which must stay below 4 GiB.
+inline bool z_fast_offsets_fit(int nx, int nz, int G, size_t complex_bytes) {
+    const unsigned long long rowb = 6ull * (unsigned long long)nkx_of(nx) * complex_bytes;
+    return ((unsigned long long)(nz - 1) * (unsigned long long)G + 1ull) * rowb <= (1ull << 32);
+}
+
 struct RowMap {
     int ny, nz, G;
     __host__ __device__ __forceinline__ long row(int z, int y) const {

@@ -89,6 +89,8 @@ _SIGS = {
     "tf_set_plan_file": ([ctypes.c_char_p], ctypes.c_int),
     "tf_tune": ([ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p,
                  ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "tf_kernel_plan": ([ctypes.POINTER(tf_grid), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "tf_profile": ([_P, ctypes.c_int32], ctypes.c_int),
     "tf_profile_read": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "tf_fno_param_count": ([ctypes.c_int32], ctypes.c_int64),
@@ -309,6 +311,15 @@ def tf_profile_read(h):
 
 def tf_set_plan_file(path):
     _check(load().tf_set_plan_file(path.encode() if path else None))
+
+
+def tf_kernel_plan(grid, precision="f32"):
+    """(row_block, fast, zvariant) that tf_create would use for the grid."""
+    rb, fast, zv = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    _check(load().tf_kernel_plan(ctypes.byref(grid_struct(grid)), prec, ctypes.byref(rb), ctypes.byref(fast),
+                                 ctypes.byref(zv)))
+    return rb.value, bool(fast.value), zv.value
 
 
 def tf_tune(sizes, precision, plan_path):

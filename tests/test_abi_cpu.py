@@ -130,3 +130,23 @@ def test_surrogate_head_weights_of_a_plain_pulse():
     w2 = tf.tf_fno_phasor_weights(configs.pulse(cep=0.5 * np.pi, pol_angle=0.5 * np.pi), 4)
     # z = exp(-i pi/2) = -i, b = 1: Re(z b) = 0, -Im(z b) = 1
     assert np.allclose(w2, [0, 0, 0, 1], atol=1e-15)
+
+
+def test_fast_z_kernel_needs_its_strip_offsets_to_fit_32_bits(monkeypatch):
+    """The fast z kernel addresses a strip with 32-bit byte offsets spanning
+    (nz - 1) row blocks of 6 nx/2 complex values: an unblocked 768 x 512 x 512
+    spectrum (4.8 GB) must fall to the generic kernels, blocked rows and the
+    unblocked 512^3 (3.2 GB) keep the fast ones.  Decided on the host."""
+    monkeypatch.delenv("TFOCUS_GENERIC_KERNELS", raising=False)
+    monkeypatch.delenv("TFOCUS_ZVARIANT", raising=False)
+    wide = dict(configs.cube_grid(512, 0.1), nx=768)
+    for grid, rb, fast in ((wide, "512", False), (wide, "8", True),
+                           (configs.cube_grid(512, 0.1), "512", True)):
+        monkeypatch.setenv("TFOCUS_ROW_BLOCK", rb)
+        got_rb, got_fast, _ = tf.tf_kernel_plan(grid, "f32")
+        assert got_rb == int(rb) and got_fast == fast, (grid["nx"], rb)
+    # the arithmetic behind the decision: last strip offset of the wide grid
+    rowb = 6 * (768 // 2) * 8
+    assert (511 * 512 + 1) * rowb > 2 ** 32 >= (511 * 8 + 1) * rowb
+    with pytest.raises(tf.TfError):
+        tf.tf_kernel_plan(dict(wide, nx=100), "f32")

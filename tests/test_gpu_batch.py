@@ -78,6 +78,50 @@ def test_batch_equals_solver_path_and_graph_replays():
     assert np.abs(outs[0]).max() > 0
 
 
+def test_graph_is_not_replayed_after_an_eager_run_with_other_arguments():
+    """A graph run, an eager run with other step counts and time steps (which
+    reorders the slots and rewrites the per-slot dt), then the first arguments
+    again: the last run must equal the first bit for bit, windows and states."""
+    inst, nsteps = instances()
+    grids = [i[0] for i in inst]
+    pulses = [i[1] for i in inst]
+    dts = [i[2] for i in inst]
+    other_steps = [3, 8, 6, 2, 11, 1, 5]
+    other_dts = [0.7 * d for d in dts]
+    n = len(inst)
+    wsz = (6, WIN["wz"], WIN["wy"], WIN["wx"])
+
+    def states(b):
+        out = []
+        for i in range(n):
+            g = grids[i]
+            st = np.empty((6, g["nz"], g["ny"], g["nx"]), np.float32)
+            b.get_fields(i, st)
+            out.append(st)
+        return out
+
+    with tf.Batch(grids, pulses, "f32") as b:
+        dst = torch.zeros((n,) + wsz, dtype=torch.float32, device="cuda")
+        b.run(nsteps, dts, WIN, dst, use_graph=True)
+        torch.cuda.synchronize()
+        first = dst.cpu().numpy()
+        first_states = states(b)
+        other = torch.zeros_like(dst)
+        b.run(other_steps, other_dts, WIN, other, use_graph=False)
+        torch.cuda.synchronize()
+        other_states = states(b)
+        dst.zero_()
+        b.run(nsteps, dts, WIN, dst, use_graph=True)
+        torch.cuda.synchronize()
+        again = dst.cpu().numpy()
+        again_states = states(b)
+    assert np.array_equal(again, first)
+    for i in range(n):
+        assert np.array_equal(again_states[i], first_states[i]), i
+    # the eager run really was another sweep
+    assert not all(np.array_equal(other_states[i], first_states[i]) for i in range(n))
+
+
 def test_batch_instances_match_oracle_jump():
     inst, nsteps = instances()
     for i in (0, 3, 5):
@@ -133,4 +177,76 @@ def test_tuner_writes_plans_that_keep_parity(tmp_path):
         ref = np.concatenate([Eo, Bo])
         assert np.linalg.norm(out - ref) / np.linalg.norm(ref) <= 1e-5
     finally:
-        tf.tf_set_plan_file(None)
+        # back to the plans every other test (and the bench) runs with
+        tf.tf_set_plan_file(os.environ.get("TFOCUS_PLAN_FILE") or tf.DEFAULT_PLANS)
+
+
+def test_C4_sweep_as_configured_equals_solver_and_matches_oracle():
+    """The batched sweep the bench times: 64 instances on {128, 192, 256}^3
+    grids drawn by seed, each with its own f-number, CEP and GDD, init + steps
+    to the focus + 64^3 cut-out, replayed from one captured graph.  Every
+    instance's final state and window equal the single-instance solver path
+    bit for bit (compared on the device); four sampled instances match the
+    oracle's exact jump (Sec. II.A) from the GPU init after the one-time
+    projection of B, and the oracle's cut-out (Eqs. (14)-(16))."""
+    insts = configs.c4()
+    assert len(insts) == 64 and {c["n"][0] for c in insts} == {128, 192, 256}
+    grids = [tf.tf_layer_grid(c["pulse"], c["n"], c["spacing"]) for c in insts]
+    for c, g in zip(insts, grids):
+        ref = pulse.layer_grid(c["pulse"], c["n"], c["spacing"])
+        assert all(g[k] == pytest.approx(ref[k], abs=1e-12) for k in ref)
+    pulses = [c["pulse"] for c in insts]
+    nsteps = [c["steps"] for c in insts]
+    dts = [c["dt"] for c in insts]
+    win = insts[0]["window"]
+    wsz = (6, win["wz"], win["wy"], win["wx"])
+    dst = torch.zeros((64,) + wsz, dtype=torch.float32, device="cuda")
+    pick = sorted(np.random.default_rng(44).choice(64, 4, replace=False).tolist())
+    finals = {}
+    with tf.Batch(grids, pulses, "f32") as b:
+        b.run(nsteps, dts, win, dst)
+        b.run(nsteps, dts, win, dst)          # a replay of the captured graph
+        torch.cuda.synchronize()
+        for i in range(64):
+            g = grids[i]
+            st = torch.empty((6, g["nz"], g["ny"], g["nx"]), dtype=torch.float32, device="cuda")
+            b.get_fields(i, st)
+            with tf.Solver(g, "f32") as s:
+                s.set_pulse(pulses[i])
+                s.advance(nsteps[i], dts[i])
+                ref = torch.empty_like(st)
+                s.get_fields(ref)
+                wref = torch.empty(wsz, dtype=torch.float32, device="cuda")
+                s.read_focal(win, wref)
+                torch.cuda.synchronize()
+            assert torch.equal(st, ref), i
+            assert torch.equal(dst[i], wref), i
+            if i in pick:
+                finals[i] = st.cpu().numpy()
+            del st, ref
+    windows = dst.cpu().numpy()
+    for i in pick:
+        g, p = grids[i], pulses[i]
+        sp = (g["dz"], g["dy"], g["dx"])
+        with tf.Solver(g, "f32") as s:
+            s.set_pulse(p)
+            init = np.empty(s.shape, np.float32)
+            s.get_fields(init)
+            s.advance(1, 0.0)
+            start = np.empty(s.shape, np.float32)
+            s.get_fields(start)
+        iz, iy, ix = (np.random.default_rng(i).integers(0, n, 3000) for n in (g["nz"], g["ny"], g["nx"]))
+        nzero = np.argwhere(np.abs(init[1]) > 0)
+        sel = nzero[np.random.default_rng(i + 1).integers(0, len(nzero), 3000)]
+        iz, iy, ix = (np.concatenate([a, sel[:, k]]) for k, a in enumerate((iz, iy, ix)))
+        E, B = pulse.init_fields_at(p, g, iz, iy, ix)
+        iref = np.concatenate([E, B])
+        assert np.abs(init[:, iz, iy, ix] - iref).max() <= 2e-7 * np.abs(iref).max(), i
+        x = start.astype(np.float64)
+        E, B = psatd.jump(x[:3], x[3:], sp, nsteps[i] * dts[i])
+        ref = np.concatenate([E, B])
+        tol = np.sqrt(nsteps[i]) * 1e-5
+        assert np.linalg.norm(finals[i] - ref) / np.linalg.norm(ref) <= tol, i
+        geo = pulse.geometry(p)
+        wref = mapping.readout(ref, g, win, nsteps[i] * dts[i], geo["R_min"], geo["R_max"])
+        assert np.linalg.norm(windows[i] - wref) <= tol * np.linalg.norm(wref), i

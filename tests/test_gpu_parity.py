@@ -249,7 +249,7 @@ def test_determinism_bitwise():
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("n", [64, 128, 192])
+@pytest.mark.parametrize("n", [64, 128, 192, 256])
 @pytest.mark.parametrize("zvariant", [0, 1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("row_block", ["8", "n"])
 def test_every_kernel_plan_keeps_parity(n, zvariant, row_block, monkeypatch):

@@ -379,6 +379,39 @@ tf_status tf_fno_loss_grad(tf_fno* f, const float* params, const float* head_w, 
 tf_status tf_fno_train_step(tf_fno* f, const float* params, const float* head_w, const float* target,
                             int32_t batch, double lr, double* loss);
 
+/* Configuration of a whole training run (tf_fno_train). */
+typedef struct {
+    int32_t epochs;          /* passes over the n samples, >= 1                      */
+    int32_t batch;           /* minibatch size, 1..max_batch, <= n                   */
+    double lr;               /* peak learning rate                                    */
+    double lr_min_frac;      /* cosine decay from lr to lr * lr_min_frac, in [0, 1]   */
+    uint64_t seed;           /* seed of the per-epoch shuffles (splitmix64)           */
+    int32_t scale_targets;   /* 1: train on targets / RMS(all targets), then fold the
+                                RMS into P2 and c2 so the operator predicts the
+                                targets (the Adam state is reset afterwards)          */
+    int32_t reserved;
+    double* epoch_loss;      /* host, nullable: epochs entries, the mean batch loss
+                                of each epoch                                          */
+} tf_train_cfg;
+
+/* A whole training run on the device: per epoch a Fisher-Yates shuffle of the
+ * n samples (host, splitmix64 from seed), then n / batch steps, each a
+ * minibatch gather (device), tf_fno_train_step's loss, gradient and Adam
+ * update with the step's cosine learning rate, and the loss logged on the
+ * device; the log is read back once per epoch.  params_dev [n][8], head_w_dev
+ * [n][K] (NULL when K = 1) and targets_dev [n][6][64][64][64] are device
+ * memory and are not modified.  final_loss (nullable) receives the last
+ * epoch's mean loss.  Synchronous.  TF_ESTATE for an inference-only
+ * surrogate; TF_ENONFINITE if the loss or the target RMS is not finite. */
+tf_status tf_fno_train(tf_fno* f, const float* params_dev, const float* head_w_dev, const float* targets_dev,
+                       int64_t n, const tf_train_cfg* cfg, double* final_loss);
+
+/* Held-out error: rel_l2 (host, n entries) receives ||out_i - y_i|| / ||y_i||
+ * for the surrogate's prediction out_i of every sample (device inputs as for
+ * tf_fno_train), in batches of max_batch.  Synchronous. */
+tf_status tf_fno_eval(tf_fno* f, const float* params_dev, const float* head_w_dev, const float* targets_dev,
+                      int64_t n, double* rel_l2);
+
 /* The operator's truncated transforms on their own (device pointers):
  * modes <- rfft3(v) on the kept modes; u <- irfft3 of the kept modes with
  * zeros elsewhere (scipy / numpy normalisation: the inverse carries 1/64^3). */

@@ -28,6 +28,16 @@ kx = 0 plane the index N-M has no kept partner).
 Mode order q = (kz_i * 2M + ky_i) * M + kx, ky_i / kz_i indexing the kept
 list ascending.  GELU(x) = x (1 + erf(x / sqrt 2)) / 2.
 Loss of a batch: mean over samples of ||out - y|| / ||y||.
+
+Training update (``adam_step``): Adam with bias correction (Kingma and Ba,
+"Adam: a method for stochastic optimization", ICLR 2015, Algorithm 1), in
+float64 on flat parameter vectors: with g the gradient of step t = 1, 2, ...
+  m <- b1 m + (1 - b1) g,   v <- b2 v + (1 - b2) g^2,
+  p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+Pinned by closed forms: the first step moves every parameter by
+lr g / (|g| + eps); a constant gradient keeps that step at every t (the bias
+corrections undo the zero start exactly); alternating g, -g gives the
+second step lr (1 - b1) / (1 + b1) g / (|g| + eps) backwards.
 """
 import math
 
@@ -204,3 +214,14 @@ def loss_and_grad(P, pb, y, hp, w=None):
     G["W0"] = _outer(c["a"], g_v)
     G["b0"] = g_v.sum(axis=(0, 2, 3, 4))
     return L, G
+
+
+def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One bias-corrected Adam step (Algorithm 1 of Kingma and Ba) on flat
+    float64 arrays; t counts steps from 1.  Returns (p, m, v) as new arrays."""
+    p, g, m, v = (np.asarray(a, dtype=np.float64) for a in (p, g, m, v))
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mhat = m / (1.0 - b1 ** t)
+    vhat = v / (1.0 - b2 ** t)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v

@@ -1026,16 +1026,63 @@ __global__ void k_to_bf16(const float* src, bf16* dst, int n) {
     if (i < n) dst[i] = (bf16)src[i];
 }
 
-__global__ void k_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
-                       float eps, float bc1, float bc2) {
+// Adam with bias correction (Kingma and Ba, Algorithm 1).  The factors
+// 1 - b1 and 1 - b2 come in rounded from float64: formed in float32 from the
+// rounded b2 = 0.999 they would be off by 1.3e-5 relative.
+__global__ void k_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float omb1,
+                       float b2, float omb2, float eps, float bc1, float bc2) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    const float mi = b1 * m[i] + omb1 * gi;
+    const float vi = b2 * v[i] + omb2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// ---- device-side training loop (tf_fno_train, tf_fno_eval) ----
+
+// Per-block float64 sums of squares over n floats (fixed grid, so the
+// partials and their host sum in block order are deterministic).
+constexpr int SQ_BLOCKS = 2048;
+__global__ __launch_bounds__(256) void k_sumsq32(const float* x, int64_t n, double* part) {
+    double s = 0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(SQ_BLOCKS) * 256) {
+        const double v = x[i];
+        s += v * v;
+    }
+    __shared__ double r[256];
+    r[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) r[threadIdx.x] += r[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = r[0];
+}
+
+// Minibatch gather: sample b of the batch is row idx[b] of the data set;
+// targets are multiplied by tscale on the way (grid: (blocks, B)).
+__global__ __launch_bounds__(256) void k_gather_targets(const float* y, const int* idx, float tscale, float* yb) {
+    const int b = blockIdx.y;
+    const float4* src = reinterpret_cast<const float4*>(y + int64_t(idx[b]) * OUT_SZ);
+    float4* dst = reinterpret_cast<float4*>(yb + int64_t(b) * OUT_SZ);
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < OUT_SZ / 4; i += int64_t(gridDim.x) * 256) {
+        float4 v = src[i];
+        v.x *= tscale; v.y *= tscale; v.z *= tscale; v.w *= tscale;
+        dst[i] = v;
+    }
+}
+__global__ void k_gather_rows(const float* p, const float* w, const int* idx, int B, int nb, float* pb, float* wb) {
+    for (int i = threadIdx.x; i < B * NPAR; i += blockDim.x) pb[i] = p[int64_t(idx[i / NPAR]) * NPAR + i % NPAR];
+    if (w)
+        for (int i = threadIdx.x; i < B * nb; i += blockDim.x) wb[i] = w[int64_t(idx[i / nb]) * nb + i % nb];
+}
+__global__ void k_log_loss(const double* res, double* log, int step) { log[step] = res[0]; }
+__global__ void k_scale(float* x, int64_t n, float s) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) x[i] *= s;
 }
 
 // ---------------------------------------------------------------------------
@@ -1192,6 +1239,7 @@ struct tf_fno {
     float *G[2] = {};
     float *out = nullptr, *gout = nullptr, *part = nullptr, *gstar = nullptr;
     bf16 *hT = nullptr, *ghT = nullptr;
+    float *pbuf = nullptr, *wbuf = nullptr, *ybuf = nullptr;   // tf_fno_train minibatches (on first use)
     double* dres = nullptr;
     double* lpart = nullptr;
 
@@ -1288,14 +1336,16 @@ Gemm g_mix(const float* X, const bf16* R, float* Yo, int B, bool trans) {
     GemmArgs g{opnd(X, plain(X3_SZ), two(5, KS * LINE, 1), MODE_Y, MODE_Z, 1),
                opnd(R, rr, rc, 4096, int64_t(KS * M) * 4096, trans ? 1 : 0),
                res(Yo, plain(X3_SZ), two(5, KS * LINE, 1), MODE_Y, MODE_Z), B, 64, 64};
-    return Gemm{g, KS * M, KS, launch<32, 64, 2, float, bf16, false>};
+    // the adjoint (trans) splits the gradient operand into bf16 hi + lo; the
+    // forward keeps one bf16 copy of the modes
+    return Gemm{g, KS * M, KS, trans ? launch<32, 64, 2, float, bf16, true> : launch<32, 64, 2, float, bf16, false>};
 }
 // G*[q][(s,c)][(s',o)] = sum_b X*[b][(s,c)] gY*[b][(s',o)]
 Gemm g_mix_grad(const float* X, const float* gY, float* gs, int B) {
     GemmArgs g{opnd(X, two(5, KS * LINE, 1), plain(X3_SZ), MODE_Y, MODE_Z, 0),
                opnd(gY, plain(X3_SZ), two(5, KS * LINE, 1), MODE_Y, MODE_Z, 0),
                res(gs, plain(64), plain(1), 4096, int64_t(KS * M) * 4096), 64, 64, B};
-    return Gemm{g, KS * M, KS, launch<64, 64, 4, float, float, false>};
+    return Gemm{g, KS * M, KS, launch<64, 64, 4, float, float, true>};
 }
 
 }  // namespace
@@ -1530,6 +1580,11 @@ tf_status reduce_into(tf_fno* f, int nparts, int len, float* dst, int groups = 1
     return launched();
 }
 
+// Backward pass.  The weight-gradient GEMMs and the adjoint of the mixing
+// take their float32 operands as bf16 hi + lo parts (three MFMAs, about
+// float32 products): a one-part bf16 copy of each activation would put a
+// relative error of up to 2^-9 on every term of sums that cancel heavily.
+// The bf16 weights themselves are exact in either form.
 tf_status backward(tf_fno* f, const float* params, const float* hw, const float* target, int B) {
     const int64_t nb = B;
     const int64_t szN = nb * NODE_SZ, sz1 = nb * X1_SZ, sz2 = nb * X2_SZ, sz3 = nb * X3_SZ;
@@ -1550,14 +1605,14 @@ tf_status backward(tf_fno* f, const float* params, const float* hw, const float*
         GemmArgs a{opnd(f->V[3], plain(1), plain(C), int64_t(CHUNK) * C, NODE_SZ, 0, C),
                    opnd(f->ghT, plain(1), plain(N3), CHUNK, int64_t(HID) * N3, 1),
                    res(f->part, plain(HID), plain(1), 33 * HID, int64_t(NCHUNK) * 33 * HID), 33, HID, CHUNK};
-        TRY(run(f, Gemm{a, NCHUNK, B, launch<64, 128, 4, float, bf16, false>}, szN, szH, szP, 4, 2));
+        TRY(run(f, Gemm{a, NCHUNK, B, launch<64, 128, 4, float, bf16, true>}, szN, szH, szP, 4, 2));
         TRY(reduce_into(f, B * NCHUNK, 33 * HID, f->grad + OFF_P1));
     }
     {   // [P2; c2] = [h | 1]^T dL/dout
         GemmArgs a{opnd(f->hT, plain(N3), plain(1), CHUNK, int64_t(HID) * N3, 1, HID),
                    opnd(f->gout, plain(1), plain(N3), CHUNK, OUT_SZ, 1),
                    res(f->part, plain(NOUT), plain(1), 129 * NOUT, int64_t(NCHUNK) * 129 * NOUT), 129, NOUT, CHUNK};
-        TRY(run(f, Gemm{a, NCHUNK, B, launch<32, 32, 1, bf16, float, false>}, szH, szO, szP, 2, 4));
+        TRY(run(f, Gemm{a, NCHUNK, B, launch<32, 32, 1, bf16, float, true>}, szH, szO, szP, 2, 4));
         // per-sample gradient of the effective head, then through the head weights
         TRY(reduce_into(f, NCHUNK, 129 * NOUT, f->geff, B));
         const int n = (HID + 1) * NOUT * f->nb;
@@ -1571,7 +1626,7 @@ tf_status backward(tf_fno* f, const float* params, const float* hw, const float*
             GemmArgs a{opnd(f->V[l], plain(1), plain(C), int64_t(CHUNK) * C, NODE_SZ, 0, C),
                        opnd(g, plain(C), plain(1), int64_t(CHUNK) * C, NODE_SZ, 0),
                        res(f->part, plain(C), plain(1), 33 * C, int64_t(NCHUNK) * 33 * C), 33, C, CHUNK};
-            TRY(run(f, Gemm{a, NCHUNK, B, launch<64, 32, 2, float, float, false>}, szN, szN, szP));
+            TRY(run(f, Gemm{a, NCHUNK, B, launch<64, 32, 2, float, float, true>}, szN, szN, szP));
             TRY(reduce_into(f, B * NCHUNK, 33 * C, f->grad + off_w(l)));
         }
         // adjoint of the inverse transform: modes gradient
@@ -1598,6 +1653,35 @@ tf_status backward(tf_fno* f, const float* params, const float* hw, const float*
     hipLaunchKernelGGL(k_lift_grad_final, dim3(1), dim3(LIFT_THREADS), 0, f->cur, f->part, params, B, f->grad);
     return launched();
 }
+
+// splitmix64 (Steele, Lea and Flood, OOPSLA 2014): the shuffles' generator.
+uint64_t splitmix64(uint64_t& st) {
+    uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Device buffers of one call, freed on every return path after the stream
+// has drained.
+struct CallBuffers {
+    hipStream_t st;
+    std::vector<void*> ptrs;
+    explicit CallBuffers(hipStream_t s) : st(s) {}
+    ~CallBuffers() {
+        if (!ptrs.empty()) (void)hipStreamSynchronize(st);
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    template <typename T>
+    tf_status alloc(T** p, int64_t n) {
+        void* q = nullptr;
+        const hipError_t e = hipMalloc(&q, size_t(n) * sizeof(T));
+        if (e != hipSuccess) return fail(TF_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        ptrs.push_back(q);
+        *p = static_cast<T*>(q);
+        return TF_OK;
+    }
+};
 
 tf_status check_batch(tf_fno* f, int B, const float* hw, bool need_w = true) {
     if (!f) return fail(TF_EINVAL, "surrogate is NULL");
@@ -1701,13 +1785,136 @@ tf_status tf_fno_train_step(tf_fno* f, const float* params, const float* head_w,
     const double b1 = 0.9, b2 = 0.999;
     const float bc1 = float(1.0 - std::pow(b1, double(f->adam_t))), bc2 = float(1.0 - std::pow(b2, double(f->adam_t)));
     hipLaunchKernelGGL(k_adam, dim3((NPARAMS + 255) / 256), dim3(256), 0, f->cur, f->prm, f->am, f->av, f->grad,
-                       NPARAMS, float(lr), float(b1), float(b2), 1e-8f, bc1, bc2);
+                       NPARAMS, float(lr), float(b1), float(1.0 - b1), float(b2), float(1.0 - b2), 1e-8f, bc1, bc2);
     TRY(launched());
     f->working_stale = true;
     if (loss) {
         TF_HIP(hipMemcpyAsync(loss, f->dres, sizeof(double), hipMemcpyDeviceToHost, f->st));
         TF_HIP(hipStreamSynchronize(f->st));
     }
+    return TF_OK;
+}
+
+tf_status tf_fno_train(tf_fno* f, const float* params, const float* head_w, const float* targets, int64_t n,
+                       const tf_train_cfg* cfg, double* final_loss) {
+    if (!f || !cfg) return fail(TF_EINVAL, "surrogate and cfg must not be NULL");
+    if (!f->training) return fail(TF_ESTATE, "surrogate was created for inference only");
+    if (!params || !targets) return fail(TF_EINVAL, "params and targets must not be NULL");
+    if (f->nb != 1 && !head_w) return fail(TF_EINVAL, "a head of several basis fields needs its weights");
+    const int B = cfg->batch;
+    if (B < 1 || B > f->maxB) return fail(TF_EINVAL, "batch must be in [1, max_batch]");
+    if (n < B || n > (int64_t(1) << 30)) return fail(TF_EINVAL, "need batch <= n < 2^30");
+    if (cfg->epochs < 1) return fail(TF_EINVAL, "epochs must be >= 1");
+    if (!std::isfinite(cfg->lr) || cfg->lr < 0.0) return fail(TF_EINVAL, "lr must be finite and >= 0");
+    if (!(cfg->lr_min_frac >= 0.0 && cfg->lr_min_frac <= 1.0)) return fail(TF_EINVAL, "lr_min_frac must be in [0, 1]");
+    TF_HIP(hipSetDevice(f->dev));
+    const int64_t NPARAMS = f->np;
+    if (!f->ybuf) {
+        TRY(f->alloc(&f->pbuf, int64_t(f->maxB) * NPAR));
+        TRY(f->alloc(&f->wbuf, int64_t(f->maxB) * f->nb));
+        TRY(f->alloc(&f->ybuf, int64_t(f->maxB) * OUT_SZ));
+    }
+    const int64_t spe = n / B, total = spe * cfg->epochs;
+    CallBuffers cb(f->st);
+    int* idx = nullptr;
+    double *log = nullptr, *part = nullptr;
+    TRY(cb.alloc(&idx, n));
+    TRY(cb.alloc(&log, spe));
+    TRY(cb.alloc(&part, SQ_BLOCKS));
+    // target scale: the root mean square of every target value
+    double scale = 1.0;
+    if (cfg->scale_targets) {
+        hipLaunchKernelGGL(k_sumsq32, dim3(SQ_BLOCKS), dim3(256), 0, f->st, targets, n * OUT_SZ, part);
+        TRY(launched());
+        std::vector<double> h(SQ_BLOCKS);
+        TF_HIP(hipMemcpyAsync(h.data(), part, SQ_BLOCKS * sizeof(double), hipMemcpyDeviceToHost, f->st));
+        TF_HIP(hipStreamSynchronize(f->st));
+        double ss = 0;
+        for (double v : h) ss += v;
+        scale = std::sqrt(ss / (double(n) * double(OUT_SZ)));
+        if (!(scale > 0.0) || !std::isfinite(scale)) return fail(TF_ENONFINITE, "targets have no finite nonzero RMS");
+    }
+    const float tscale = float(1.0 / scale);
+    std::vector<int> perm(n);
+    std::vector<double> hlog(spe);
+    uint64_t rng = cfg->seed;
+    double last = 0.0;
+    f->cur = f->st;
+    const double b1 = 0.9, b2 = 0.999;
+    for (int ep = 0; ep < cfg->epochs; ++ep) {
+        // Fisher-Yates shuffle of the sample order
+        for (int64_t i = 0; i < n; ++i) perm[i] = int(i);
+        for (int64_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[splitmix64(rng) % uint64_t(i + 1)]);
+        TF_HIP(hipMemcpyAsync(idx, perm.data(), n * sizeof(int), hipMemcpyHostToDevice, f->st));
+        for (int64_t k = 0; k < spe; ++k) {
+            const int* bi = idx + k * B;
+            hipLaunchKernelGGL(k_gather_rows, dim3(1), dim3(256), 0, f->st, params, f->nb != 1 ? head_w : nullptr, bi,
+                               B, f->nb, f->pbuf, f->wbuf);
+            hipLaunchKernelGGL(k_gather_targets, dim3(512, B), dim3(256), 0, f->st, targets, bi, tscale, f->ybuf);
+            TRY(launched());
+            const float* hw = f->nb != 1 ? f->wbuf : nullptr;
+            TRY(forward(f, f->pbuf, hw, B, f->out));
+            TRY(backward(f, f->pbuf, hw, f->ybuf, B));
+            // cosine decay from lr to lr * lr_min_frac over all steps
+            const double step = double(ep) * double(spe) + double(k);
+            const double a = cfg->lr * (cfg->lr_min_frac +
+                                        (1.0 - cfg->lr_min_frac) * 0.5 * (1.0 + std::cos(M_PI * step / double(total))));
+            f->adam_t += 1;
+            const float bc1 = float(1.0 - std::pow(b1, double(f->adam_t)));
+            const float bc2 = float(1.0 - std::pow(b2, double(f->adam_t)));
+            hipLaunchKernelGGL(k_adam, dim3((NPARAMS + 255) / 256), dim3(256), 0, f->st, f->prm, f->am, f->av, f->grad,
+                               NPARAMS, float(a), float(b1), float(1.0 - b1), float(b2), float(1.0 - b2), 1e-8f, bc1,
+                               bc2);
+            hipLaunchKernelGGL(k_log_loss, dim3(1), dim3(1), 0, f->st, f->dres, log, int(k));
+            TRY(launched());
+            f->working_stale = true;
+        }
+        TF_HIP(hipMemcpyAsync(hlog.data(), log, spe * sizeof(double), hipMemcpyDeviceToHost, f->st));
+        TF_HIP(hipStreamSynchronize(f->st));
+        double m = 0;
+        for (double v : hlog) m += v;
+        last = m / double(spe);
+        if (cfg->epoch_loss) cfg->epoch_loss[ep] = last;
+        if (!std::isfinite(last)) return fail(TF_ENONFINITE, "training loss is not finite");
+    }
+    if (cfg->scale_targets) {
+        // fold the scale into the projection so the operator predicts the
+        // targets themselves; the Adam moments no longer match: reset them
+        const int64_t m = NPARAMS - OFF_P2;
+        hipLaunchKernelGGL(k_scale, dim3((m + 255) / 256), dim3(256), 0, f->st, f->prm + OFF_P2, m, float(scale));
+        TRY(launched());
+        TF_HIP(hipMemsetAsync(f->am, 0, NPARAMS * sizeof(float), f->st));
+        TF_HIP(hipMemsetAsync(f->av, 0, NPARAMS * sizeof(float), f->st));
+        f->adam_t = 0;
+        f->working_stale = true;
+    }
+    TF_HIP(hipStreamSynchronize(f->st));
+    if (final_loss) *final_loss = last;
+    return TF_OK;
+}
+
+tf_status tf_fno_eval(tf_fno* f, const float* params, const float* head_w, const float* targets, int64_t n,
+                      double* rel_l2) {
+    if (!f || !params || !targets || !rel_l2) return fail(TF_EINVAL, "NULL argument");
+    if (f->nb != 1 && !head_w) return fail(TF_EINVAL, "a head of several basis fields needs its weights");
+    if (n < 1 || n > (int64_t(1) << 30)) return fail(TF_EINVAL, "need 1 <= n < 2^30");
+    TF_HIP(hipSetDevice(f->dev));
+    CallBuffers cb(f->st);
+    double* res = nullptr;
+    TRY(cb.alloc(&res, n));
+    f->cur = f->st;
+    for (int64_t i0 = 0; i0 < n; i0 += f->maxB) {
+        const int nb = int(std::min<int64_t>(f->maxB, n - i0));
+        TRY(forward(f, params + i0 * NPAR, f->nb != 1 ? head_w + i0 * f->nb : nullptr, nb, f->out));
+        hipLaunchKernelGGL(k_loss_part, dim3(LOSS_CH, nb), dim3(256), 0, f->st, f->out, targets + i0 * OUT_SZ,
+                           f->lpart);
+        hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(LOSS_THREADS), 0, f->st, f->lpart, LOSS_CH, nb, f->dres,
+                           f->dres + 1 + nb);
+        TRY(launched());
+        TF_HIP(hipMemcpyAsync(res + i0, f->dres + 1 + nb, nb * sizeof(double), hipMemcpyDeviceToDevice, f->st));
+    }
+    TF_HIP(hipMemcpyAsync(rel_l2, res, n * sizeof(double), hipMemcpyDeviceToHost, f->st));
+    TF_HIP(hipStreamSynchronize(f->st));
     return TF_OK;
 }
 
@@ -1775,8 +1982,12 @@ tf_status tf_fno_load(tf_fno* f, const char* path) {
             std::fclose(fp);
             return fail(TF_EINVAL, "truncated checkpoint");
         }
-        TF_HIP(hipMemcpyAsync(dsts[k], h.data(), NPARAMS * sizeof(float), hipMemcpyHostToDevice, f->st));
-        TF_HIP(hipStreamSynchronize(f->st));
+        hipError_t e = hipMemcpyAsync(dsts[k], h.data(), NPARAMS * sizeof(float), hipMemcpyHostToDevice, f->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(f->st);
+        if (e != hipSuccess) {
+            std::fclose(fp);
+            return fail(TF_EDEVICE, std::string("checkpoint upload: ") + hipGetErrorString(e));
+        }
     }
     std::fclose(fp);
     if (f->training) {

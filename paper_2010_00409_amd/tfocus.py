@@ -58,6 +58,12 @@ class tf_window(ctypes.Structure):
                 ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("cz", ctypes.c_double)]
 
 
+class tf_train_cfg(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("lr_min_frac", ctypes.c_double), ("seed", ctypes.c_uint64), ("scale_targets", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("epoch_loss", ctypes.POINTER(ctypes.c_double))]
+
+
 _P = ctypes.c_void_p
 _SIGS = {
     "tf_version": ([], ctypes.c_char_p),
@@ -105,6 +111,9 @@ _SIGS = {
     "tf_fno_loss_grad": ([_P, _P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
     "tf_fno_train_step": ([_P, _P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)],
                           ctypes.c_int),
+    "tf_fno_train": ([_P, _P, _P, _P, ctypes.c_int64, ctypes.POINTER(tf_train_cfg), ctypes.POINTER(ctypes.c_double)],
+                     ctypes.c_int),
+    "tf_fno_eval": ([_P, _P, _P, _P, ctypes.c_int64, _P], ctypes.c_int),
     "tf_fno_spectral_forward": ([_P, _P, ctypes.c_int32, _P], ctypes.c_int),
     "tf_fno_spectral_inverse": ([_P, _P, ctypes.c_int32, _P], ctypes.c_int),
     "tf_fno_save": ([_P, ctypes.c_char_p], ctypes.c_int),
@@ -619,6 +628,36 @@ class Surrogate:
         _check(load().tf_fno_train_step(self.h, pp, self._w(w, B), pt, B, float(lr),
                                          ctypes.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
+
+    def train(self, p, target, epochs, batch, lr, w=None, lr_min_frac=0.02, seed=0, scale_targets=True):
+        """tf_fno_train over n samples (device tensors p [n, 8], w [n, K],
+        target [n, 6, 64, 64, 64]); returns the per-epoch mean losses."""
+        import numpy as np
+        n = p.shape[0]
+        pp = self._dev(p, (n, FNO_NPARAM), "params")
+        pt = self._dev(target, (n, FNO_NOUT, FNO_N, FNO_N, FNO_N), "target")
+        pw = None
+        if self.nbasis != 1:
+            pw = self._dev(w, (n, self.nbasis), "head weights")
+        hist = np.zeros(int(epochs), dtype=np.float64)
+        cfg = tf_train_cfg(int(epochs), int(batch), float(lr), float(lr_min_frac), int(seed),
+                           1 if scale_targets else 0, 0, hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        last = ctypes.c_double()
+        _check(load().tf_fno_train(self.h, pp, pw, pt, int(n), ctypes.byref(cfg), ctypes.byref(last)))
+        return hist
+
+    def eval(self, p, target, w=None):
+        """tf_fno_eval: per-sample relative L2 error (numpy array)."""
+        import numpy as np
+        n = p.shape[0]
+        pp = self._dev(p, (n, FNO_NPARAM), "params")
+        pt = self._dev(target, (n, FNO_NOUT, FNO_N, FNO_N, FNO_N), "target")
+        pw = None
+        if self.nbasis != 1:
+            pw = self._dev(w, (n, self.nbasis), "head weights")
+        out = np.zeros(int(n), dtype=np.float64)
+        _check(load().tf_fno_eval(self.h, pp, pw, pt, int(n), out.ctypes.data))
+        return out
 
     def spectral_forward(self, v, modes):
         B = v.shape[0]

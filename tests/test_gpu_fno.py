@@ -6,6 +6,8 @@ them to MFMA (W_l, R_l, P1, P2), so the remaining differences are the GPU's
 bf16 rounding of the activations that enter those contractions and fp32
 accumulation.  The truncated transforms alone use split-bf16 products and
 must match to about fp32 accuracy."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -21,9 +23,20 @@ SPECTRAL_TOL = 2e-5       # split-bf16 products (about 16 mantissa bits) with fp
 # rounded operand sets lie on the path from the parameters to the output
 # (mixing input, pointwise input and weights per layer, projection input,
 # hidden layer and the two projection weights), mostly averaging out in the
-# contractions: the forward output stays within 1e-2 in relative L2.
-FORWARD_TOL = 1e-2
-GRAD_TOL = 3e-2           # as above, plus the bf16 hidden-layer gradient of the projection
+# contractions: the forward output stays within 5e-3 in relative L2.
+FORWARD_TOL = 5e-3
+# Gradients: the backward pass's own rounding (weight-gradient GEMMs in split
+# bf16, about float32; one bf16 copy of the stored hidden layer and of the
+# data-gradient operands) stays within 1e-2 (relative L2) for residuals with
+# a structured part and for white residuals four times the output.  The loss
+# gradient is J^T applied to the residual out - y (J the network's Jacobian),
+# and the GPU's residual also carries the forward's bf16 error (gated above):
+# that error lies in the range of J, white noise mostly does not, so when a
+# white residual dominates, J^T amplifies the forward error's share.  At white
+# residuals of 0.5 (output about 1e-2 of that) the four-basis head measures
+# 1.2e-2; that case is held to 1.5e-2.
+GRAD_TOL = 1e-2
+GRAD_TOL_WHITE = 1.5e-2
 GRAD_COS = 0.999
 
 
@@ -158,14 +171,23 @@ def test_four_basis_head_forward_matches_oracle():
         assert rel(got[b], ref[b]) <= FORWARD_TOL, b
 
 
+@pytest.mark.parametrize("residual, gate", [("structured", GRAD_TOL), ("white2", GRAD_TOL),
+                                             ("white0.5", GRAD_TOL_WHITE)])
 @pytest.mark.parametrize("nbasis", [1, 4])
-def test_gradient_matches_oracle(nbasis):
+def test_gradient_matches_oracle(nbasis, residual, gate):
+    """Residuals: another network's output plus 0.1 white noise
+    (structured), or pure white noise of 2 or 0.5 around the output."""
     hp = fno.HP(nbasis=nbasis)
     P = make_params(7, hp=hp)
     rng = np.random.default_rng(8)
     pb = rng.uniform(size=(2, 8)).astype(np.float32).astype(np.float64)
     w = head_weights(rng, 2, nbasis) if nbasis > 1 else None
-    y = (fno.forward(P, pb, hp, w=w) + 0.5 * rng.standard_normal((2, 6, 64, 64, 64))).astype(np.float32)
+    noise = rng.standard_normal((2, 6, 64, 64, 64))
+    if residual == "structured":
+        y = fno.forward(make_params(17, hp=hp), pb, hp, w=w) + 0.1 * noise
+    else:
+        y = fno.forward(P, pb, hp, w=w) + {"white2": 2.0, "white0.5": 0.5}[residual] * noise
+    y = y.astype(np.float32)
     L_ref, G_ref = fno.loss_and_grad(P, pb, y.astype(np.float64), hp, w=w)
     with tf.Surrogate(2, training=True, nbasis=nbasis) as s:
         s.set_params(P)
@@ -173,11 +195,15 @@ def test_gradient_matches_oracle(nbasis):
         L, g = s.loss_grad(torch.from_numpy(pb.astype(np.float32)).cuda(), torch.from_numpy(y).cuda(), wd)
     G = tf.fno_unflatten(g)
     assert L == pytest.approx(L_ref, rel=FORWARD_TOL)
+    errs = {}
     for k, ref in G_ref.items():
         got = G[k]
         e = rel(got, ref)
         cos = float(np.real(np.vdot(got.ravel(), ref.ravel())) / (np.linalg.norm(got) * np.linalg.norm(ref)))
-        assert e <= GRAD_TOL and cos >= GRAD_COS, (k, e, cos)
+        errs[k] = (e, cos)
+    print(f"nbasis {nbasis} residual {residual}: worst {max(e for e, _ in errs.values()):.2e} (gate {gate:.1e})")
+    for k, (e, cos) in errs.items():
+        assert e <= gate and cos >= GRAD_COS, (k, e, cos, gate)
 
 
 def test_adam_steps_reduce_the_loss_and_checkpoint_roundtrips(tmp_path):
@@ -220,3 +246,161 @@ def test_graph_inference_replays_equal_eager_forward():
                 torch.cuda.synchronize()
                 del junk
                 assert torch.equal(out, ref)
+
+
+def read_checkpoint(path, nparams):
+    """Adam step, parameters and both moments of a training checkpoint (four
+    int64: magic, version, parameter count, step; then float32 parameters,
+    first and second moments)."""
+    raw = open(path, "rb").read()
+    hdr = np.frombuffer(raw[:32], np.int64)
+    body = np.frombuffer(raw[32:], np.float32).astype(np.float64)
+    assert hdr[2] == nparams and body.size == 3 * nparams
+    return int(hdr[3]), body[:nparams], body[nparams:2 * nparams], body[2 * nparams:]
+
+
+def test_adam_steps_match_oracle_adam(tmp_path):
+    """Three tf_fno_train_step updates against the oracle's float64 Adam
+    (Kingma and Ba, Algorithm 1) fed the same gradients: the GPU's own
+    gradient at each step (tf_fno_loss_grad, deterministic, so train_step
+    sees the same values).  Parameters after every step and both moments
+    after the last, element by element."""
+    P = make_params(9, r_scale=1.0)
+    rng = np.random.default_rng(10)
+    pb = rng.uniform(size=(2, 8)).astype(np.float32)
+    y = np.ascontiguousarray(fno.forward(make_params(12), pb.astype(np.float64), HP), dtype=np.float32)
+    pd, yd = torch.from_numpy(pb).cuda(), torch.from_numpy(y).cuda()
+    lrs = (1e-3, 3e-3, 2e-3)
+    with tf.Surrogate(2, training=True) as s:
+        s.set_params(P)
+        p = s.get_params().astype(np.float64)
+        m, v = np.zeros_like(p), np.zeros_like(p)
+        gmax = np.zeros_like(p)
+        for t, lr in enumerate(lrs, 1):
+            _, g = s.loss_grad(pd, yd)
+            _, g2 = s.loss_grad(pd, yd)
+            assert np.array_equal(g, g2)
+            g = g.astype(np.float64)
+            gmax = np.maximum(gmax, np.abs(g))
+            s.train_step(pd, yd, lr, want_loss=False)
+            p, m, v = fno.adam_step(p, g, m, v, t, lr)
+            got = s.get_params().astype(np.float64)
+            # float32 rounding of each update (relative 1e-6) and of the stored parameters
+            tol = 4 * 2.0 ** -24 * np.abs(p) + 2e-6 * t * max(lrs)
+            bad = np.abs(got - p) > tol
+            assert not bad.any(), (t, int(bad.sum()), float(np.abs(got - p).max()))
+        path = tmp_path / "adam.ckpt"
+        s.save(path)
+    step, pg, mg, vg = read_checkpoint(path, p.size)
+    assert step == 3
+    assert np.all(np.abs(mg - m) <= 1e-6 * gmax + 1e-38)
+    assert np.all(np.abs(vg - v) <= 1e-6 * v + 1e-6 * 1e-3 * gmax ** 2 + 1e-38)
+    assert np.abs(pg - p).max() <= np.abs(got - p).max()
+
+
+def splitmix_perms(seed, n, epochs):
+    """Per-epoch Fisher-Yates permutations drawn with splitmix64 (Steele, Lea
+    and Flood, OOPSLA 2014), as the library's training loop documents."""
+    M = (1 << 64) - 1
+    st = seed
+
+    def nxt():
+        nonlocal st
+        st = (st + 0x9E3779B97F4A7C15) & M
+        z = st
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        return z ^ (z >> 31)
+
+    out = []
+    for _ in range(epochs):
+        perm = list(range(n))
+        for i in range(n - 1, 0, -1):
+            j = nxt() % (i + 1)
+            perm[i], perm[j] = perm[j], perm[i]
+        out.append(perm)
+    return out
+
+
+def _train_data(n, nbasis, seed):
+    rng = np.random.default_rng(seed)
+    P = make_params(seed, r_scale=1.0, hp=fno.HP(nbasis=nbasis))
+    pb = rng.uniform(size=(n, 8)).astype(np.float32)
+    y = (0.3 * rng.standard_normal((n, 6, 64, 64, 64))).astype(np.float32)
+    w = head_weights(rng, n, nbasis).astype(np.float32) if nbasis > 1 else None
+    return P, pb, y, w
+
+
+@pytest.mark.parametrize("nbasis", [1, 4])
+def test_training_run_equals_train_steps_over_its_shuffle(nbasis):
+    """tf_fno_train (shuffle, gather, cosine learning rate, Adam, loss log on
+    the device) against tf_fno_train_step driven from the host over the same
+    permutations and learning rates: the same parameters bit for bit and the
+    same per-epoch mean losses."""
+    n, B, E, lr, fmin, seed = 6, 2, 2, 1e-3, 0.1, 5
+    P, pb, y, w = _train_data(n, nbasis, 31)
+    pd, yd = torch.from_numpy(pb).cuda(), torch.from_numpy(y).cuda()
+    wd = None if w is None else torch.from_numpy(w).cuda()
+    with tf.Surrogate(B, training=True, nbasis=nbasis) as s:
+        s.set_params(P)
+        hist = s.train(pd, yd, E, B, lr, w=wd, lr_min_frac=fmin, seed=seed, scale_targets=False)
+        got = s.get_params()
+    spe, total = n // B, (n // B) * E
+    with tf.Surrogate(B, training=True, nbasis=nbasis) as s:
+        s.set_params(P)
+        means = []
+        for ep, perm in enumerate(splitmix_perms(seed, n, E)):
+            acc = []
+            for k in range(spe):
+                idx = torch.tensor(perm[k * B:(k + 1) * B], device="cuda")
+                step = ep * spe + k
+                a = lr * (fmin + (1 - fmin) * 0.5 * (1 + math.cos(math.pi * step / total)))
+                acc.append(s.train_step(pd[idx].contiguous(), yd[idx].contiguous(), a,
+                                        None if wd is None else wd[idx].contiguous()))
+            means.append(sum(acc) / len(acc))
+        ref = s.get_params()
+    assert np.array_equal(got, ref)
+    assert np.allclose(hist, means, rtol=1e-12)
+
+
+def test_training_run_folds_the_target_rms_into_the_projection():
+    """With lr = 0 only the scaling acts: the parameters before P2 stay as
+    set, and P2 and c2 come back multiplied by the root mean square of every
+    target value."""
+    n = 4
+    P, pb, y, _ = _train_data(n, 1, 32)
+    flat0 = tf.fno_flatten(P).astype(np.float32)
+    with tf.Surrogate(2, training=True) as s:
+        s.set_params(P)
+        s.train(torch.from_numpy(pb).cuda(), torch.from_numpy(y).cuda(), 1, 2, 0.0, seed=1)
+        got = s.get_params()
+    rms = float(np.sqrt(np.mean(y.astype(np.float64) ** 2)))
+    off = fno_p2_offset()
+    assert np.array_equal(got[:off], flat0[:off])
+    assert np.allclose(got[off:], flat0[off:].astype(np.float64) * rms, rtol=2e-7, atol=0)
+
+
+def fno_p2_offset():
+    off = 0
+    for name, shape in tf.fno_param_shapes(1):
+        if name == "P2":
+            return off
+        off += int(np.prod(shape)) * (2 if name.startswith("R") else 1)
+    raise AssertionError("no P2")
+
+
+def test_eval_gives_per_window_relative_errors_of_the_forward_pass():
+    n = 5
+    P, pb, y, _ = _train_data(n, 1, 33)
+    pd, yd = torch.from_numpy(pb).cuda(), torch.from_numpy(y).cuda()
+    with tf.Surrogate(2) as s:
+        s.set_params(P)
+        err = s.eval(pd, yd)
+        out = torch.empty_like(yd)
+        for i in range(0, n, 2):
+            s.forward(pd[i:i + 2].contiguous(), out[i:i + 2])
+        torch.cuda.synchronize()
+    o = out.cpu().numpy().astype(np.float64).reshape(n, -1)
+    t = y.astype(np.float64).reshape(n, -1)
+    ref = np.linalg.norm(o - t, axis=1) / np.linalg.norm(t, axis=1)
+    assert np.allclose(err, ref, rtol=1e-12)

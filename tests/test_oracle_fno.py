@@ -74,3 +74,66 @@ def test_phasor_head_is_the_plain_head_when_the_weights_select_one_group():
     o = fno.forward(P, pb, hp4, w=np.array([[0.0, 0.0, 1.0, 0.0]]))
     P1 = dict(P, P2=P["P2"][:, 12:18], c2=P["c2"][12:18])
     assert np.array_equal(o, fno.forward(P1, pb, tiny(1)))
+
+
+# ---- Adam (Kingma and Ba, Algorithm 1), pinned by hand-derived closed forms
+
+def _grads(seed, n=257):
+    g = np.random.default_rng(seed).normal(size=n) * np.logspace(-6, 3, n)
+    g[::17] = 0.0
+    return g
+
+
+def test_adam_first_step_is_lr_times_sign_like_ratio():
+    """t = 1: m_hat = g and v_hat = g^2 exactly, so p moves by lr g / (|g| + eps)."""
+    g = _grads(1)
+    p0 = np.random.default_rng(2).normal(size=g.size)
+    lr = 3e-3
+    p1, m, v = fno.adam_step(p0, g, np.zeros_like(g), np.zeros_like(g), 1, lr)
+    assert np.allclose(p1 - p0, -lr * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-18)
+    assert np.allclose(m, 0.1 * g, rtol=1e-15) and np.allclose(v, 0.001 * g * g, rtol=1e-12)
+    assert np.array_equal(p1[g == 0.0], p0[g == 0.0])
+
+
+def test_adam_constant_gradient_moves_by_the_same_step_every_time():
+    """The bias corrections undo the zero start: with a constant gradient
+    m_hat = g and v_hat = g^2 at every t (a wrong exponent or a missing
+    correction breaks this from t = 2 on)."""
+    g = _grads(3)
+    p = np.zeros_like(g)
+    m, v = np.zeros_like(g), np.zeros_like(g)
+    lr = 1e-2
+    step = -lr * g / (np.abs(g) + 1e-8)
+    for t in range(1, 8):
+        q, m, v = fno.adam_step(p, g, m, v, t, lr)
+        assert np.allclose(q - p, step, rtol=1e-9, atol=1e-20), t
+        p = q
+
+
+def test_adam_alternating_gradient_second_step():
+    """g then -g: m_2 = -(1 - b1)^2 g, so m_hat_2 = -(1 - b1) g / (1 + b1);
+    v_2 = (1 - b2)(1 + b2) g^2, so v_hat_2 = g^2.  The second step moves p by
+    +lr (1 - b1) / (1 + b1) g / (|g| + eps) (b1 and b2 swapped would give
+    (1 - b2) / (1 + b2) instead)."""
+    g = _grads(4)
+    p0 = np.zeros_like(g)
+    lr = 2e-3
+    p1, m, v = fno.adam_step(p0, g, np.zeros_like(g), np.zeros_like(g), 1, lr)
+    p2, m, v = fno.adam_step(p1, -g, m, v, 2, lr)
+    expect = lr * (0.1 / 1.9) * g / (np.abs(g) + 1e-8)
+    assert np.allclose(p2 - p1, expect, rtol=1e-9, atol=1e-20)
+    assert np.allclose(m, -(0.1 ** 2) * g, rtol=1e-12, atol=1e-300)
+
+
+def test_adam_is_invariant_to_gradient_scale_without_eps():
+    """With eps = 0 the update depends on g only through m / sqrt(v), which
+    scaling every gradient by c > 0 leaves unchanged."""
+    rng = np.random.default_rng(5)
+    gs = [rng.normal(size=64) for _ in range(5)]
+    runs = []
+    for c in (1.0, 1e3):
+        p, m, v = np.zeros(64), np.zeros(64), np.zeros(64)
+        for t, g in enumerate(gs, 1):
+            p, m, v = fno.adam_step(p, c * g, m, v, t, 1e-2, eps=0.0)
+        runs.append(p)
+    assert np.allclose(runs[0], runs[1], rtol=1e-12, atol=1e-15)

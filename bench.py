@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1, help="untimed runs")
     ap.add_argument("--psatd-steps", type=int, default=None, help="override steps per run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "surrogate"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "surrogate", "verify"])
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate timing on c3/c2")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
@@ -69,29 +69,86 @@ def traffic_record(kernel):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(n, seed=3):
-    """The oracle's spectral step (float64 real FFTs, Eqs. (3)-(4)) on one
-    n^3 state with random fields: a bounded sample of the workload's step."""
+def cpu_model():
+    """CPU model string of this host (/proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _median_step(fn, reps=3):
+    """Median wall time of reps calls after one untimed warm-up call (which
+    also builds the FFT plans); returns (seconds, last result)."""
+    out = fn()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2], out
+
+
+def cpu_baseline(start, cfg, focus_step, window_gpu, t_focus, mid=256, single=128):
+    """The oracle (float64 scipy rfftn -> Eqs. (3)-(4) -> irfftn) timed on
+    this host: median of 3 steps after a warm-up at the workload's size (the
+    exact jump from the GPU's start state to the focus, a step like any
+    other) and at 256^3 (random fields) with every host core, and
+    single-threaded at 128^3 for ns per cell next to the paper's CPU figure.
+    The 512^3 jump also gives the parity of the GPU's focal window against the
+    float64 oracle (relative L2 and max |error| / peak, Sec. III.A)."""
     import numpy as np
-    from oracle import psatd
-    rng = np.random.default_rng(seed)
-    E = rng.standard_normal((3, n, n, n))
-    B = rng.standard_normal((3, n, n, n))
-    d = 1.0 / 12.0
+    from oracle import mapping, psatd, pulse
     cores = psatd._workers()
-    t0 = time.perf_counter()
-    psatd.step_fft(E, B, (d, d, d), 1.0 / 24.0, workers=cores)
-    dt = time.perf_counter() - t0
-    return {"value": n ** 3 / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"one float64 oracle step (scipy rfftn -> Eqs. (3)-(4) -> irfftn, "
-                      f"{cores} workers) of a {n}^3 six-component state: {dt:.2f} s"}
+    geo = pulse.geometry(cfg["pulse"])
+    n = start.shape[1:]
+    sp = tuple(cfg["spacing"][::-1])
+    x = start.astype(np.float64)
+    T = focus_step * cfg["dt"]
+    t_big, (E, B) = _median_step(lambda: psatd.jump(x[:3], x[3:], sp, T, workers=cores))
+    ref = np.concatenate([E, B])
+    del E, B, x
+    wref = mapping.readout(ref, cfg["grid"], cfg["window"], t_focus, geo["R_min"], geo["R_max"])
+    del ref
+    wgpu = window_gpu.astype(np.float64)
+    peak = float(np.abs(wref).max())
+    parity = {"against": f"float64 oracle: one exact jump of {focus_step} dt from the GPU state after the "
+                         "one-time removal of longitudinal B (a dt = 0 step of tf_set_pulse's init), then the cut-out",
+              "window_rel_l2": float(np.linalg.norm(wgpu - wref) / np.linalg.norm(wref)),
+              "window_max_abs_over_peak": float(np.abs(wgpu - wref).max() / peak),
+              "window_peak_abs": peak,
+              "gate_rel_l2": math.sqrt(focus_step) * 1e-5}
+    rng = np.random.default_rng(3)
+    m = mid
+    y = rng.standard_normal((6, m, m, m))
+    d = cfg["spacing"][0]
+    t_mid, _ = _median_step(lambda: psatd.step_fft(y[:3], y[3:], (d, d, d), cfg["dt"], workers=cores))
+    del y
+    k = single
+    z = rng.standard_normal((6, k, k, k))
+    t_one, _ = _median_step(lambda: psatd.step_fft(z[:3], z[3:], (d, d, d), cfg["dt"], workers=1))
+    cells = n[0] * n[1] * n[2]
+    base = {
+        "value": cells / t_big, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+        "cpu_model": cpu_model(),
+        "sample": (f"median of 3 float64 oracle steps after one warm-up at {n[2]}x{n[1]}x{n[0]} "
+                   f"({cores} scipy workers; each the exact jump to the focus): {t_big:.2f} s per step"),
+        f"at_{m}": {"cell_updates_per_s": m ** 3 / t_mid, "s_per_step": t_mid, "cores": cores,
+                   "sample": "median of 3 steps after one warm-up, random fields"},
+        f"single_thread_{k}": {"ns_per_cell": t_one / k ** 3 * 1e9, "s_per_step": t_one, "cores": 1,
+                              "paper_context": "230 ns per cell per iteration, float64, single thread, "
+                                               "Xeon Gold 6154 with MKL (Sec. III.A; other hardware, context only)"},
+    }
+    return base, parity
 
 
 # surrogate training report whose held-out error the bench quotes (written by
 # python -m paper_2010_00409_amd.surrogate on MI355X; the weights themselves
 # are not kept, and inference time does not depend on their values)
-SURROGATE_REPORTS = ("surrogate_k4_head_4000x230_batch4.json", "surrogate_k4_head_4000x320_batch8.json", "surrogate_k4_head_4000x400.json", "surrogate_k4_head_4000x340.json", "surrogate_k4_head_4000x200.json",
-                     "surrogate_k4_head_4000x140.json", "surrogate_k4_head_4000x60.json")
+SURROGATE_REPORTS = ("surrogate_k4_head_4000x230_batch4.json",)
 
 
 def surrogate_inference_bytes(batch):
@@ -192,6 +249,34 @@ def bench_c4(args):
     }), flush=True)
 
 
+def bench_verify(args):
+    """The method against direct computation (Sec. III.A, Fig. 4a): a 512^3
+    direct cube and periodic layers of D/L = 1.5 ... 6 at 12 points per
+    wavelength, f = 0.3, L = 2, eps = 0.1, R0 = 16, one exact step to the
+    focus; focal error (max |diff| / peak) and the time and memory the layers
+    save, in float32 and float64."""
+    import torch
+    from paper_2010_00409_amd import verify
+
+    torch.cuda.set_device(0)
+    layers = (36, 48, 54, 64, 72, 96, 108, 144)
+    res = {prec: verify.mapped_vs_direct(layers, precision=prec, reps=max(args.steps, 1))
+           for prec in ("f32", "f64")}
+    at3 = [r for r in res["f32"]["layers"] if r["nx"] == 72][0]
+    print(json.dumps({
+        "metric": "mapped layer vs direct cube: focal error (max |diff| / peak) at D/L = 3, f = 0.3",
+        "value": at3["max_err_over_peak"], "unit": "fraction of peak", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": at3["seconds"] * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "Sec. III.A verification: 512^3 direct cube vs periodic layers nx x 512 x 512, "
+                               "dx = lambda/12, one step of dt = R0 = 16, 64^3 focal window through the cut-out"},
+        "paper_context": "0.9% at D_min/L ~ 1.9 and under 0.1% at D/L ~ 3.5 (12 points/lambda); 0.12% at "
+                         "D/L = 3.5 with time cut almost 6x (48 points/lambda); MVS-10P CPU node, float64",
+        "sweep": {prec: {"D_min_over_L": r["D_min_over_L"], "direct_seconds": r["direct_seconds"],
+                         "direct_bytes": r["direct_bytes"], "layers": r["layers"]} for prec, r in res.items()},
+    }), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -200,6 +285,9 @@ def main():
         sys.exit(2)
     if args.workload == "c4":
         bench_c4(args)
+        return
+    if args.workload == "verify":
+        bench_verify(args)
         return
     if args.workload == "surrogate":
         sec = surrogate_section(reps=max(args.steps, 1))
@@ -230,6 +318,7 @@ def main():
     # the focal window is read when the pulse centre reaches the focus
     focus_step = min(steps, int(round(cfg["pulse"]["R0"] / cfg["dt"])))
 
+    cfg = dict(cfg, grid=grid)
     with tf.Solver(grid, prec, stream) as s:
         def run():
             s.set_pulse(cfg["pulse"])
@@ -250,6 +339,16 @@ def main():
         prof = s.profile_read()
         s.profile(False)
         peak_field = float(out.abs().max().item())
+        t_focus = focus_step * cfg["dt"]
+        if not args.no_cpu_baseline:
+            # outside the timed region: the oracle's start state (the init after
+            # the one-time removal of longitudinal B) and the timed run's window
+            import numpy as np
+            s.set_pulse(cfg["pulse"])
+            s.advance(1, 0.0)
+            start = np.empty(s.shape, dtype=np.float32 if prec == "f32" else np.float64)
+            s.get_fields(start)
+            window_gpu = out.cpu().numpy()
 
     if args.calibrate_copy:
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -305,7 +404,8 @@ def main():
     if not args.no_surrogate:
         line["surrogate"] = surrogate_section()
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(n[0])
+        line["cpu_baseline"], line["parity"] = cpu_baseline(start, cfg, focus_step, window_gpu, t_focus)
+        del start
     print(json.dumps(line), flush=True)
 
 

@@ -81,3 +81,31 @@ def test_surrogate_bytes_grow_by_one_window_per_window():
     per = bench.surrogate_inference_bytes(2) - bench.surrogate_inference_bytes(1)
     assert per == bench.surrogate_inference_bytes(65) - bench.surrogate_inference_bytes(64)
     assert 300e6 < per < 450e6       # every tensor of one window written once and read once
+
+
+def test_cpu_baseline_protocol_and_parity_on_a_small_layer():
+    """The oracle leg of the bench on a small layer: warm-up + median of 3 at
+    each size, cores and CPU model reported, and the parity object computed
+    against the oracle's jump + cut-out (zero when the 'GPU' window is the
+    oracle's own)."""
+    import numpy as np
+    from oracle import mapping, psatd, pulse
+    from synthetic import configs
+    p = configs.pulse(envelope="spectral", bandwidth=0.4, R0=4.0, L=3.0, f_number=0.5, nfreq=64)
+    n, d = (24, 48, 48), 0.2
+    grid = pulse.layer_grid(p, n, (d, d, d))
+    E, B = pulse.init_fields(p, grid)
+    E, B = psatd.step_fft(E, B, (d, d, d), 0.0, project_b_first=True)
+    start = np.concatenate([E, B]).astype(np.float32)
+    cfg = dict(spacing=(d, d, d), dt=0.1, pulse=p, grid=grid,
+               window=dict(wx=8, wy=8, wz=8, cx=0.0, cy=0.0, cz=0.0))
+    x = start.astype(np.float64)
+    E, B = psatd.jump(x[:3], x[3:], (d, d, d), 40 * 0.1)
+    geo = pulse.geometry(p)
+    w = mapping.readout(np.concatenate([E, B]), grid, cfg["window"], 4.0, geo["R_min"], geo["R_max"])
+    base, par = bench.cpu_baseline(start, cfg, 40, w, 4.0, mid=16, single=8)
+    assert base["kind"] == "oracle" and base["cores"] >= 1 and base["value"] > 0
+    assert "cpu_model" in base and base["single_thread_8"]["cores"] == 1
+    assert base["at_16"]["s_per_step"] > 0 and "median of 3" in base["sample"]
+    assert par["window_rel_l2"] <= 1e-15 and par["window_max_abs_over_peak"] <= 1e-15
+    assert par["window_peak_abs"] > 0 and par["gate_rel_l2"] == pytest.approx(40 ** 0.5 * 1e-5)

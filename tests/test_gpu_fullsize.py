@@ -95,7 +95,11 @@ def test_C2_one_step_and_jump_to_focus(c2_state):
     assert rel(wgpu.astype(np.float64), wref) <= 20 * F32_STEP_TOL
 
 
-def test_C3_fullsize_init_sampled_and_one_step():
+def test_C3_fullsize_init_sampled_and_projected_first_step():
+    """The bench's first step: tf_set_pulse, then one step that also removes
+    the longitudinal part of B, against the oracle's float64 step (with the
+    same one-time projection) from the GPU's float32 init; the init itself
+    against the oracle's closed forms at sampled nodes."""
     c = configs.c3()
     grid = pulse.layer_grid(c["pulse"], c["n"], c["spacing"])
     sp = (grid["dz"], grid["dy"], grid["dx"])
@@ -103,9 +107,6 @@ def test_C3_fullsize_init_sampled_and_one_step():
         s.set_pulse(c["pulse"])
         init = np.empty(s.shape, np.float32)
         s.get_fields(init)
-        # one plain step from the raw init (set_fields clears the pending
-        # B projection, matching the oracle's step without it)
-        s.set_fields(init)
         s.advance(1, c["dt"])
         one = np.empty(s.shape, np.float32)
         s.get_fields(one)
@@ -116,9 +117,65 @@ def test_C3_fullsize_init_sampled_and_one_step():
     assert np.abs(init[:, iz, iy, ix].astype(np.float64) - ref).max() <= 2e-7 * np.abs(ref).max()
     x = init.astype(np.float64)
     del init
-    Eo, Bo = psatd.step_fft(x[:3], x[3:], sp, c["dt"])
+    Eo, Bo = psatd.step_fft(x[:3], x[3:], sp, c["dt"], project_b_first=True)
     del x
     assert rel(one.astype(np.float64), np.concatenate([Eo, Bo])) <= F32_STEP_TOL
+
+
+def test_C3_bench_run_matches_oracle_jump_at_focus_and_at_step_1000():
+    """The headline run exactly as the bench times it: tf_set_pulse, 384 steps
+    (the first also removes longitudinal B), the 64^3 focal window, then the
+    remaining 616 steps.  Reference: the oracle's single exact jump
+    (Sec. II.A) from the GPU's init after that one-time projection (a dt = 0
+    step), by 384 dt and by 1000 dt, with the cut-out of Eqs. (14)-(16) at the
+    focus.  Float32 rounding accumulates as a random walk: the gates are
+    sqrt(steps) times the per-step tolerance."""
+    c = configs.c3()
+    grid = pulse.layer_grid(c["pulse"], c["n"], c["spacing"])
+    sp = (grid["dz"], grid["dy"], grid["dx"])
+    dt, steps, win = c["dt"], c["steps"], c["window"]
+    nf = int(round(c["pulse"]["R0"] / dt))
+    assert nf == 384
+    with tf.Solver(grid, "f32") as s:
+        s.set_pulse(c["pulse"])
+        s.advance(1, 0.0)
+        start = np.empty(s.shape, np.float32)
+        s.get_fields(start)
+        s.set_pulse(c["pulse"])
+        s.advance(nf, dt)
+        wgpu = np.empty((6, win["wz"], win["wy"], win["wx"]), np.float32)
+        s.read_focal(win, wgpu)
+        t_focus = s.t
+        at_focus = np.empty(s.shape, np.float32)
+        s.get_fields(at_focus)
+        s.advance(steps - nf, dt)
+        end = np.empty(s.shape, np.float32)
+        s.get_fields(end)
+        assert s.t == pytest.approx(steps * dt)
+    x = start.astype(np.float64)
+    del start
+    Ej, Bj = psatd.jump(x[:3], x[3:], sp, nf * dt)
+    ref = np.concatenate([Ej, Bj])
+    del Ej, Bj
+    e_focus = rel(at_focus.astype(np.float64), ref)
+    del at_focus
+    geo = pulse.geometry(c["pulse"])
+    wref = mapping.readout(ref, grid, win, t_focus, geo["R_min"], geo["R_max"])
+    del ref
+    e_win = rel(wgpu.astype(np.float64), wref)
+    peak = np.abs(wref).max()
+    e_peak = float(np.abs(wgpu.astype(np.float64) - wref).max() / peak)
+    Ej, Bj = psatd.jump(x[:3], x[3:], sp, steps * dt)
+    del x
+    ref = np.concatenate([Ej, Bj])
+    del Ej, Bj
+    e_end = rel(end.astype(np.float64), ref)
+    print(f"C3 vs oracle jump: state at focus {e_focus:.2e}, window {e_win:.2e} "
+          f"(max/peak {e_peak:.2e}), state at step {steps} {e_end:.2e}")
+    assert peak > 1.0                                   # the focus is inside the window
+    assert e_focus <= math.sqrt(nf) * F32_STEP_TOL
+    assert e_win <= math.sqrt(nf) * F32_STEP_TOL
+    assert e_end <= math.sqrt(steps) * F32_STEP_TOL
 
 
 def test_C3_fullsize_planewaves_closed_form_and_invariants():

@@ -528,7 +528,9 @@ tf_status tf_tune(const int32_t* sizes, int32_t n, int32_t precision, const char
             p.fast = false;
             cands.push_back(p);
             if (!fast_offsets_fit(g, rb, precision)) continue;
-            for (int zv = 0; zv < 7; ++zv) {
+            // variants 7 and 8 (one wave per mode) exist for 512-point z
+            // columns; elsewhere they run variant 6
+            for (int zv = 0; zv < (N == 512 ? 9 : 7); ++zv) {
                 p.fast = true;
                 p.zvariant = zv;
                 cands.push_back(p);

@@ -229,17 +229,44 @@ def test_graph_replayed_steps_equal_eager_steps_bitwise(prec):
     assert rel(outs[1][0].astype(np.float64), np.concatenate([Eo, Bo])) <= tol
 
 
-@pytest.mark.parametrize("zvariant", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("zvariant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 def test_every_z_variant_at_length_512(zvariant, monkeypatch):
-    """512-point z columns (where variants 5 and 6 differ, and residues are
-    parked in LDS or held in registers) on a thin grid, two steps against
-    the oracle."""
+    """512-point z columns (where variants 5 and 6 differ, residues are
+    parked in LDS or held in registers, and variants 7 and 8 run one wave per
+    mode) on a thin grid, two steps against the oracle."""
     monkeypatch.setenv("TFOCUS_ZVARIANT", str(zvariant))
     g, st = transverse_state(40 + zvariant, (512, 8, 16), 0.3)
     st = st.astype(np.float32).astype(np.float64)
     out, _ = run_gpu(g, "f32", st, 2, 0.41)
     Eo, Bo = psatd.step_fft(st[:3], st[3:], spacing(g), 0.41, nsteps=2)
     assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= 2 * F32_TOL
+
+
+@pytest.mark.parametrize("zvariant", [7, 8])
+def test_wave_z_kernel_projection_and_huge_phases(zvariant, monkeypatch):
+    """The one-wave-per-mode z kernel on 512-point columns: the first step
+    after tf_set_pulse (which also removes longitudinal B) against the
+    oracle's step with the same projection, and a step of unstructured fields
+    (longitudinal E present) with phases c |k| dt up to 1e5 rad."""
+    monkeypatch.setenv("TFOCUS_ZVARIANT", str(zvariant))
+    p = configs.pulse(envelope="spectral", bandwidth=0.4, R0=4.0, L=3.0, f_number=0.5, nfreq=64, cep=0.7)
+    g = pulse.layer_grid(p, (32, 16, 512), (0.2, 0.2, 0.2))
+    with tf.Solver(g, "f32") as s:
+        s.set_pulse(p)
+        init = np.empty(s.shape, np.float32)
+        s.get_fields(init)
+        s.advance(1, 0.37)
+        out = np.empty(s.shape, np.float32)
+        s.get_fields(out)
+    x = init.astype(np.float64)
+    Eo, Bo = psatd.step_fft(x[:3], x[3:], spacing(g), 0.37, project_b_first=True)
+    assert np.abs(x).max() > 0.1
+    assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= F32_TOL
+    y = np.random.default_rng(zvariant).standard_normal((6, 512, 16, 32)).astype(np.float32)
+    g2 = dict(g, x_min=0.0, y_min=0.0, z_min=0.0)
+    out2, _ = run_gpu(g2, "f32", y, 1, 1.0e4)
+    Eo, Bo = psatd.step_fft(y[:3].astype(np.float64), y[3:].astype(np.float64), spacing(g2), 1.0e4)
+    assert rel(out2.astype(np.float64), np.concatenate([Eo, Bo])) <= F32_TOL
 
 
 def test_determinism_bitwise():

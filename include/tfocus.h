@@ -218,6 +218,27 @@ tf_status tf_time(const tf_solver* s, double* t);
 tf_status tf_get_grid(const tf_solver* s, tf_grid* grid);
 
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the steps of
+ * tf_advance applied in place to a caller-owned state, with no allocation and
+ * no solver object.  state_dev: [6][nz][ny][nx] of the precision's element
+ * type, device memory on the current device; advanced by nsteps steps of dt
+ * (Eqs. (3)-(4) between forward and inverse 3-D FFTs, the conventions of
+ * tf_advance); project_b_first = 1 also removes the longitudinal part of B in
+ * the first step, as the first tf_advance after tf_set_pulse does.  Kernel
+ * plans as tf_create.  The spectrum and twiddle tables live in a static
+ * 128 MiB device array that every call on a device shares (each device holds
+ * its own until the process ends): a grid needing more gives TF_ENOMEM before
+ * any HIP call (about 5.5 M cells in float32, 2.7 M in float64: 128^3 fits
+ * in both).  Nothing in it must start at zero (each call rebuilds the tables
+ * and each step rewrites the spectrum), but calls on one device whose work
+ * overlaps in time race on it.  Only kernel launches are queued on hip_stream
+ * (NULL: the null stream), so the call may be captured into a graph; the
+ * first call on a device looks the array up (hipGetSymbolAddress) and should
+ * be made outside capture (nsteps = 0 does only that). */
+tf_status tf_advance_noalloc(const tf_grid* grid, int32_t precision, void* state_dev, int64_t nsteps, double dt,
+                             int32_t project_b_first, void* hip_stream);
+
 /* Pass kinds reported by tf_profile_read. */
 typedef enum {
     TF_PASS_X_FORWARD = 0, TF_PASS_Y_FORWARD = 1, TF_PASS_Z_STEP = 2, TF_PASS_Y_INVERSE = 3,

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -163,9 +164,110 @@ void free_all(tf_solver* s) {
         if (p) (void)hipFree(p);
 }
 
+// ---- allocation-free stepping (tf_advance_noalloc) ----
+
+// Device scratch of tf_advance_noalloc: the twiddle tables of the three axes,
+// then the half spectrum of the grid being advanced.  One copy per device,
+// held until the process ends; every call on a device reuses it.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of this device's scratch array, looked up once per device
+// with that device current.  The array's name is only a host-side stand-in.
+tf_status noalloc_scratch(int dev, void** out) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(TF_EUNSUPPORTED, "device ordinal beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        TF_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(TF_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return TF_OK;
+}
+
+// Bytes of scratch tf_advance_noalloc needs for a grid: the twiddle tables
+// (nx + ny + nz complex, rounded up to 256 bytes), then the half spectrum.
+size_t noalloc_tw_bytes(const tf_grid& g, size_t esize) {
+    return (2 * esize * (size_t)(g.nx + g.ny + g.nz) + 255) / 256 * 256;
+}
+size_t noalloc_spec_bytes(const tf_grid& g, size_t esize) {
+    return (size_t)g.nz * g.ny * tf::nkx_of(g.nx) * 6 * 2 * esize;
+}
+
+// Twiddle tables of the three axes, exp(-2 pi i e / n) for e < n, laid out
+// x, then y, then z (interleaved re, im): the float64 angle 2 pi e / n and its
+// sine and cosine, rounded to the element type.
+template <typename T>
+__global__ void k_noalloc_twiddles(T* tw, int nx, int ny, int nz) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nx + ny + nz) return;
+    int n = nx, e = i;
+    if (i >= nx + ny) { n = nz; e = i - nx - ny; }
+    else if (i >= nx) { n = ny; e = i - nx; }
+    const double a = 2.0 * M_PI * (double)e / (double)n;
+    double sn, cs;
+    sincos(a, &sn, &cs);
+    tw[2 * i] = T(cs);
+    tw[2 * i + 1] = T(-sn);
+}
+
+template <typename T>
+hipError_t noalloc_steps(const tf_grid& g, void* state, unsigned char* base, int64_t nsteps, double dt,
+                         bool project_b_first, int precision, hipStream_t st) {
+    const size_t es = sizeof(T);
+    T* tw = reinterpret_cast<T*>(base);
+    void* spec = base + noalloc_tw_bytes(g, es);
+    const int nt = g.nx + g.ny + g.nz;
+    hipLaunchKernelGGL(k_noalloc_twiddles<T>, dim3((nt + 255) / 256), dim3(256), 0, st, tw, g.nx, g.ny, g.nz);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    void* tws[3] = {tw, tw + 2 * g.nx, tw + 2 * (g.nx + g.ny)};
+    const KernelPlan kp = plan_for(g, precision);
+    const tf::RowMap rm{g.ny, g.nz, kp.row_block};
+    for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k)
+        e = step_passes<T>(state, spec, tws, g, rm, kp, dt, project_b_first && k == 0, tf::Batch{}, st);
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
+
+tf_status tf_advance_noalloc(const tf_grid* grid, int32_t precision, void* state_dev, int64_t nsteps, double dt,
+                             int32_t project_b_first, void* hip_stream) {
+    if (!state_dev) return fail(TF_EINVAL, "state_dev is NULL");
+    if (precision != TF_F32 && precision != TF_F64) return fail(TF_EINVAL, "precision must be TF_F32 or TF_F64");
+    tf_status vs = validate_grid(grid);
+    if (vs != TF_OK) return vs;
+    if (nsteps < 0) return fail(TF_EINVAL, "nsteps must be >= 0");
+    if (!std::isfinite(dt)) return fail(TF_EINVAL, "dt must be finite");
+    const size_t es = precision == TF_F64 ? 8 : 4;
+    const size_t need = noalloc_tw_bytes(*grid, es) + noalloc_spec_bytes(*grid, es);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(TF_ENOMEM, "grid needs " + std::to_string(need) + " bytes of scratch; the allocation-free path holds " +
+                                   std::to_string(NOALLOC_SCRATCH_BYTES));
+    int dev = 0;
+    TF_HIP(hipGetDevice(&dev));
+    void* base = nullptr;
+    tf_status st = noalloc_scratch(dev, &base);
+    if (st != TF_OK) return st;
+    if (nsteps == 0) return TF_OK;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const hipError_t e =
+        precision == TF_F64
+            ? noalloc_steps<double>(*grid, state_dev, static_cast<unsigned char*>(base), nsteps, dt, project_b_first != 0,
+                                    precision, stream)
+            : noalloc_steps<float>(*grid, state_dev, static_cast<unsigned char*>(base), nsteps, dt, project_b_first != 0,
+                                   precision, stream);
+    if (e != hipSuccess) return fail(TF_EDEVICE, std::string("tf_advance_noalloc: ") + hipGetErrorString(e));
+    return TF_OK;
+}
 
 const char* tf_version(void) { return "tfocus 0.1"; }
 

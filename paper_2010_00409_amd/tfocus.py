@@ -95,6 +95,8 @@ _SIGS = {
     "tf_set_plan_file": ([ctypes.c_char_p], ctypes.c_int),
     "tf_tune": ([ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p,
                  ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "tf_advance_noalloc": ([ctypes.POINTER(tf_grid), ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_double,
+                            ctypes.c_int32, _P], ctypes.c_int),
     "tf_kernel_plan": ([ctypes.POINTER(tf_grid), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "tf_profile": ([_P, ctypes.c_int32], ctypes.c_int),
@@ -320,6 +322,19 @@ def tf_profile_read(h):
 
 def tf_set_plan_file(path):
     _check(load().tf_set_plan_file(path.encode() if path else None))
+
+
+def tf_advance_noalloc(grid, precision, state, nsteps, dt, project_b_first=False, stream=None):
+    """Advance a device state [6][nz][ny][nx] in place without allocating."""
+    ptr, dev, nbytes, isz = _buffer(state)
+    if not dev:
+        raise ValueError("tf_advance_noalloc needs a device state")
+    prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    g = grid_struct(grid)
+    if isz != (8 if prec == TF_F64 else 4) or nbytes != 6 * g.nx * g.ny * g.nz * isz:
+        raise ValueError("state must hold 6 nx ny nz elements of the precision's type")
+    _check(load().tf_advance_noalloc(ctypes.byref(g), prec, ctypes.c_void_p(ptr), int(nsteps),
+                                     float(dt), 1 if project_b_first else 0, _stream_ptr(stream)))
 
 
 def tf_kernel_plan(grid, precision="f32"):

@@ -2,6 +2,8 @@
 
     python -m paper_2010_00409_amd.profile_summary stats DIR
         per-kernel calls, total and mean duration from a --kernel-trace run
+    python -m paper_2010_00409_amd.profile_summary counters DIR [DIR ...]
+        mean of every counter per dispatch, per kernel, from --pmc runs
     python -m paper_2010_00409_amd.profile_summary traffic FETCH_DIR WRITE_DIR [--json OUT]
         mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) per kernel from two
         --pmc runs, scaled by the factor that makes a plain device copy of
@@ -45,7 +47,7 @@ def _gemm_args(name):
 def _short(name):
     if "k_gemm" in name:                      # surrogate GEMM: keep the tile shape and types
         return "k_gemm<" + _gemm_args(name) + ">"
-    for key in ("k_z_fast", "k_col_fast", "k_x_forward", "k_x_inverse", "k_init_map", "k_readout",
+    for key in ("k_z_fast", "k_z_wave", "k_col_fast", "k_x_forward", "k_x_inverse", "k_init_map", "k_readout",
                 "k_lift_x", "k_line_fwd", "k_line_proj", "k_lineout", "k_proj", "k_head_eff",
                 "k_col", "k_z", "k_sumsq", "k_reduce", "copy"):
         if key in name:
@@ -93,6 +95,28 @@ def counters(d, counter):
     for name, _, v in dispatches(d, counter):
         per.setdefault(name, []).append(v)
     return {k: sum(v) / len(v) for k, v in per.items()}
+
+
+def counter_table(dirs, kernels=None):
+    """Markdown table: per kernel (short name), the mean per dispatch of every
+    counter found in the --pmc runs under dirs."""
+    per = {}
+    names = []
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    k, c = _short(r["Kernel_Name"]), r["Counter_Name"]
+                    if kernels and k not in kernels:
+                        continue
+                    per.setdefault(k, {}).setdefault(c, []).append(float(r["Counter_Value"]))
+                    if c not in names:
+                        names.append(c)
+    out = ["| kernel | " + " | ".join(names) + " |", "|---|" + "---|" * len(names)]
+    for k in sorted(per):
+        vals = [per[k].get(c) for c in names]
+        out.append(f"| {k} | " + " | ".join(f"{sum(v) / len(v):.4g}" if v else "" for v in vals) + " |")
+    return "\n".join(out)
 
 
 def copy_value(d, counter):
@@ -153,6 +177,8 @@ if __name__ == "__main__":
     mode = sys.argv[1]
     if mode == "stats":
         print(stats(sys.argv[2])[0])
+    elif mode == "counters":
+        print(counter_table(sys.argv[2:]))
     elif mode == "traffic":
         text, rec, _ = traffic(sys.argv[2], sys.argv[3])
         print(text)

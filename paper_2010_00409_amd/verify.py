@@ -1,4 +1,5 @@
-"""The method against direct computation (Sec. III.A), on the library.
+"""The method against direct computation (Sec. III.A) and the paper's
+focusing examples (Sec. III.B.1-2), on the library.
 
 The paper verifies the mapping on its most demanding case: a flat-top pulse
 of f-number 0.3 (opening angle about 1 rad), length L = 2 wavelengths, edge
@@ -17,6 +18,7 @@ exceeds the pulse's whole x-extent, so every node has one preimage.  Both
 windows are read through the same cut-out, so the comparison covers the
 region the method returns.
 """
+import math
 import time
 
 from . import tfocus as tf
@@ -92,3 +94,106 @@ def mapped_vs_direct(layer_nx, points_per_lambda=12, side=512, window=64, precis
     return dict(pulse=p, precision=precision, points_per_lambda=points_per_lambda, side=side, window=window,
                 D_min=geo["D_min"], D_min_over_L=geo["D_min"] / p["L"], direct_seconds=t_direct,
                 direct_bytes=device_bytes(direct, precision), peak=peak, layers=rows)
+
+
+# ---------------------------------------------------------------- intensity scans
+def intensity_scan(grid, pulse, window, t0, t1, dt, precision="f32", follow=False):
+    """Peak of |E|^2 over a window and over the times t0, t0 + dt, ... <= t1
+    (one exact jump to t0, then steps of dt), read through the cut-out.  With
+    follow the window centre moves with the pulse centre along the axis,
+    x = t - R0.  Returns (peak |E|^2, time of the peak, node (x, y, z) of the
+    peak).  Every node's field oscillates at the carrier, so with a few
+    dozen snapshots per period the largest |E|^2 is the squared amplitude."""
+    import numpy as np
+    dtype = np.float64 if precision == "f64" else np.float32
+    w = np.empty((6, window["wz"], window["wy"], window["wx"]), dtype=dtype)
+    best = (-1.0, 0.0, (0.0, 0.0, 0.0))
+    n = int(math.floor((t1 - t0) / dt + 1e-9)) + 1
+    with tf.Solver(grid, precision) as s:
+        s.set_pulse(pulse)
+        s.advance(1, t0)
+        for k in range(n):
+            t = t0 + k * dt
+            win = dict(window, cx=window["cx"] + (t - pulse["R0"] if follow else 0.0))
+            s.read_focal(win, w)
+            e2 = (w[:3].astype(np.float64) ** 2).sum(axis=0)
+            i = int(np.argmax(e2))
+            if e2.flat[i] > best[0]:
+                iz, iy, ix = np.unravel_index(i, e2.shape)
+                ic = math.floor((win["cx"] - grid["x_min"]) / grid["dx"] + 0.5)
+                jc = math.floor((win["cy"] - grid["y_min"]) / grid["dy"] + 0.5)
+                kc = math.floor((win["cz"] - grid["z_min"]) / grid["dz"] + 0.5)
+                pos = (grid["x_min"] + (ic + ix - win["wx"] // 2) * grid["dx"],
+                       grid["y_min"] + (jc + iy - win["wy"] // 2) * grid["dy"],
+                       grid["z_min"] + (kc + iz - win["wz"] // 2) * grid["dz"])
+                best = (float(e2.flat[i]), t, pos)
+            if k + 1 < n:
+                s.advance(1, dt)
+    return best
+
+
+def intensity(e2_peak):
+    """Cycle-averaged intensity of a field of squared amplitude |E|^2:
+    |E|^2 / (8 pi) (c = 1, the paper's CGS form; the library's amplitude
+    makes the cycle-averaged power through the sphere P0)."""
+    return e2_peak / (8.0 * math.pi)
+
+
+# ---------------------------------------------------------------- Sec. III.B.1
+# Gaussian temporal and angular profiles: u_l = sin(k zeta) exp(-zeta^2 ln 4 /
+# (n lambda)^2) with n = 4 wavelengths (intensity FWHM), u_ts =
+# exp(-theta^2 / theta0^2) with tan theta0 = 1 / (2 f), R0 = 20 lambda,
+# P0 = 1, on 512 nodes over 40 lambda per axis.  The envelope is cut at
+# |zeta| <= L / 2 = 10 lambda, where it has fallen to 1.7e-4.
+GAUSS_PULSE = dict(VERIFY_PULSE, envelope="gauss", transverse="gauss", R0=20.0, L=20.0, ncycles=4.0,
+                   f_number=1.0)
+
+
+def paraxial_peak_intensity(f_number, P0=1.0, wavelength=1.0):
+    """Peak intensity of a paraxial Gaussian beam of power P0 focused at
+    f-number f: I0 = 2 P0 / (pi w0^2) with waist w0 = 2 f lambda / pi
+    (Sec. III.B.1)."""
+    w0 = 2.0 * f_number * wavelength / math.pi
+    return 2.0 * P0 / (math.pi * w0 * w0)
+
+
+def gaussian_beam_vs_paraxial(f_numbers, n=512, side=40.0, window=48, span=1.0, dt=1.0 / 32, precision="f32",
+                              pulse=None):
+    """Peak intensity at the focus of the Gaussian beam of Sec. III.B.1 for
+    each f-number (times R0 - span ... R0 + span), the paraxial prediction
+    and their ratio."""
+    rows = []
+    base = dict(GAUSS_PULSE if pulse is None else pulse)
+    for f in f_numbers:
+        p = dict(base, f_number=float(f))
+        d = side / n
+        g = tf.tf_layer_grid(p, (n, n, n), (d, d, d))
+        win = dict(wx=window, wy=window, wz=window, cx=0.0, cy=0.0, cz=0.0)
+        e2, t, pos = intensity_scan(g, p, win, p["R0"] - span, p["R0"] + span, dt, precision)
+        I, I0 = intensity(e2), paraxial_peak_intensity(f, p["P0"], p["wavelength"])
+        rows.append(dict(f_number=float(f), peak_intensity=I, paraxial=I0, ratio=I / I0, t_peak=t,
+                         peak_position=list(pos)))
+    return rows
+
+
+# ---------------------------------------------------------------- Sec. III.B.2
+def flattop_peak_vs_f(f_numbers, nx=128, nt=1024, window=(64, 48, 48), t_span=(-3.0, 6.0), dt=1.0 / 32,
+                      precision="f32", pulse=None):
+    """Peak cycle-averaged intensity of the flat-top pulse of Sec. III.A
+    (L = 2, eps = 0.1, R0 = 16, P0 = 1) and where and when it is reached, for
+    each f-number, in a layer of D = 2 L (Sec. III.B.2: the scheme's error
+    stays under 1% of the peak there) of nx nodes along x and nt x nt
+    transversely at equal spacing.  The window follows the pulse centre along
+    the axis from t = R0 + t_span[0] to R0 + t_span[1]."""
+    rows = []
+    base = dict(VERIFY_PULSE if pulse is None else pulse)
+    for f in f_numbers:
+        p = dict(base, f_number=float(f))
+        d = 2.0 * p["L"] / nx
+        g = tf.tf_layer_grid(p, (nx, nt, nt), (d, d, d))
+        win = dict(wx=window[0], wy=window[1], wz=window[2], cx=0.0, cy=0.0, cz=0.0)
+        e2, t, pos = intensity_scan(g, p, win, p["R0"] + t_span[0], p["R0"] + t_span[1], dt, precision,
+                                    follow=True)
+        rows.append(dict(f_number=float(f), theta=tf.tf_pulse_geometry(p)["theta"], peak_intensity=intensity(e2),
+                         t_peak=t, x_peak=pos[0], peak_position=list(pos)))
+    return rows

@@ -57,3 +57,55 @@ def test_reduced_mapped_vs_direct_matches_oracle():
     assert errs[0] > errs[1] > errs[2]
     assert errs[1] < 0.015 and errs[2] < 0.01
     torch.cuda.synchronize()
+
+
+def oracle_scan(p, grid, window, t0, t1, dt, follow=False):
+    """The oracle's intensity scan: init, one exact jump to t0 (removing
+    longitudinal B), then steps of dt, each read through the cut-out."""
+    g = pulse.geometry(p)
+    sp = (grid["dz"], grid["dy"], grid["dx"])
+    E, B = pulse.init_fields(p, grid)
+    E, B = psatd.step_fft(E, B, sp, t0, 1, project_b_first=True)
+    n = int(np.floor((t1 - t0) / dt + 1e-9)) + 1
+    best = (-1.0, 0.0, None)
+    for k in range(n):
+        t = t0 + k * dt
+        win = dict(window, cx=window["cx"] + (t - p["R0"] if follow else 0.0))
+        w = mapping.readout(np.concatenate([E, B]), grid, win, t, g["R_min"], g["R_max"])
+        e2 = (w[:3] ** 2).sum(axis=0)
+        i = int(np.argmax(e2))
+        if e2.flat[i] > best[0]:
+            best = (float(e2.flat[i]), t, np.unravel_index(i, e2.shape))
+        if k + 1 < n:
+            E, B = psatd.step_fft(E, B, sp, dt)
+    return best
+
+
+def test_gaussian_beam_scan_matches_oracle():
+    """Sec. III.B.1 pipeline at reduced size (R0 = 6, 2 cycles, f = 1, 64^3
+    nodes over 12 wavelengths): the peak |E|^2 at the focus over a time scan,
+    float64 GPU against the oracle."""
+    p = dict(verify.GAUSS_PULSE, R0=6.0, L=8.0, ncycles=2.0, f_number=1.0)
+    d = 12.0 / 64
+    grid = pulse.layer_grid(p, (64, 64, 64), (d, d, d))
+    win = dict(wx=16, wy=16, wz=16, cx=0.0, cy=0.0, cz=0.0)
+    e2, t, pos = verify.intensity_scan(grid, p, win, 5.0, 7.0, 0.125, "f64")
+    r2, rt, _ = oracle_scan(p, grid, win, 5.0, 7.0, 0.125)
+    assert e2 == pytest.approx(r2, rel=1e-11) and t == rt
+    assert verify.paraxial_peak_intensity(1.0) == pytest.approx(np.pi / 2)      # 2 P0 / (pi (2/pi)^2)
+
+
+def test_flattop_peak_scan_matches_oracle():
+    """Sec. III.B.2 pipeline at reduced size (R0 = 6, f = 0.5, D = 2 L on 32 x
+    128 x 128 nodes): the window follows the pulse along the axis; the peak
+    |E|^2, its time and node, float64 GPU against the oracle."""
+    p = dict(verify.VERIFY_PULSE, R0=6.0, f_number=0.5)
+    d = 2 * p["L"] / 32
+    grid = pulse.layer_grid(p, (32, 128, 128), (d, d, d))
+    win = dict(wx=32, wy=24, wz=24, cx=0.0, cy=0.0, cz=0.0)
+    e2, t, pos = verify.intensity_scan(grid, p, win, 4.0, 9.0, 0.125, "f64", follow=True)
+    r2, rt, ri = oracle_scan(p, grid, win, 4.0, 9.0, 0.125, follow=True)
+    assert e2 == pytest.approx(r2, rel=1e-11) and t == rt
+    # the oracle's node (z, y, x) in the window gives the same position
+    x = grid["x_min"] + (np.floor((t - p["R0"] - grid["x_min"]) / d + 0.5) + ri[2] - 16) * d
+    assert pos[0] == pytest.approx(x, abs=1e-9)

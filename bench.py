@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--psatd-steps", type=int, default=None, help="override steps per run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "surrogate", "verify", "paraxial",
-                                                         "flattop"])
+                                                         "flattop", "duplicate"])
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate timing on c3/c2")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
@@ -260,6 +260,19 @@ def bench_verify(args):
     from paper_2010_00409_amd import verify
 
     torch.cuda.set_device(0)
+    if args.workload == "duplicate":
+        dup = verify.transverse_duplication((64, 96, 128, 192, 256), reps=max(args.steps, 1))
+        at = [r for r in dup["boxes"] if r["n_t"] == 128][0]
+        print(json.dumps({
+            "metric": "transverse duplication: focal error (max |diff| / peak) of a 128^2 transverse box",
+            "value": at["max_err_over_peak"], "unit": "fraction of peak", "n_gpus": 1, "steps": args.steps,
+            "warmup": 1, "ms_per_step": at["seconds"] * 1e3, "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "Sec. II.C closing remarks: Sec. III.A pulse, layer of 128 nodes (D/L = 5.33) "
+                                   "at dx = lambda/12, transverse boxes replicated along y and z against the "
+                                   "512^2 layer, one step to the focus, 64^3 window"},
+            "sweep": dup}), flush=True)
+        return
     layers = (32, 48, 64, 96, 128, 192)           # D/L = 1.33 (overlapping) ... 8
     res = {prec: verify.mapped_vs_direct(layers, precision=prec, reps=max(args.steps, 1))
            for prec in ("f32", "f64")}
@@ -317,7 +330,7 @@ def main():
     if args.workload == "c4":
         bench_c4(args)
         return
-    if args.workload == "verify":
+    if args.workload in ("verify", "duplicate"):
         bench_verify(args)
         return
     if args.workload in ("paraxial", "flattop"):

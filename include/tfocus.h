@@ -81,7 +81,11 @@ typedef enum {
 typedef struct {
     int32_t nx, ny, nz;   /* nx even; each length a product of 2s and 3s,
                              8 <= n <= 1024 (tf_supported_length)               */
-    int32_t reserved;
+    int32_t replicate_yz; /* 0: the grid holds the pulse transversely.  1: y and
+                             z are periods of the mapping too (transverse
+                             duplication, Sec. II.C closing remarks): every
+                             node also sums the replicas y + m ny dy,
+                             z + l nz dz, and focal windows wrap in y and z   */
     double dx, dy, dz;    /* > 0                                                 */
     double x_min, y_min, z_min;
 } tf_grid;
@@ -122,7 +126,8 @@ typedef struct {
 
 /* Node-aligned focal window of wx*wy*wz nodes centred on the node nearest
  * (cx, cy, cz); node i along x is centre + i - wx/2.  x wraps (mapping T,
- * Eq. (13)); y and z must stay inside the grid. */
+ * Eq. (13)); y and z must stay inside the grid unless it replicates the pulse
+ * transversely (replicate_yz), where they wrap as x does. */
 typedef struct {
     int32_t wx, wy, wz, reserved;
     double cx, cy, cz;
@@ -176,7 +181,8 @@ tf_status tf_state_ptr(tf_solver* s, void** dev_ptr);
 
 /* Initialise E and B from the pulse, Eqs. (5)-(11), mapped into the layer:
  * every node sums the pulse over its preimages x + n D (Eq. (13) and the
- * superposition remark after Eq. (12)).  Sets t = 0 and the cut-out radii,
+ * superposition remark after Eq. (12)), and with replicate_yz also over
+ * y + m ny dy, z + l nz dz.  Sets t = 0 and the cut-out radii,
  * and makes the next tf_advance remove the longitudinal part of B once
  * (E loses its longitudinal part at every step, Eq. (3)).
  * TF_EDOMAIN if D = nx dx <= L.  info (nullable) receives the geometry. */

@@ -16,7 +16,12 @@ Readings: {a} = a - floor(a); t is the time since the start of the run,
 so the geometric focus is reached at t = R0/c.  The focal window is
 node-aligned: its centre snaps to node floor((c - min)/d + 1/2), node i of
 the window is centre + i - w//2 (unwrapped), x wraps modulo nx (this is T
-on nodes) and y, z must stay inside the grid (no transverse wrap).
+on nodes) and y, z must stay inside the grid, unless the grid replicates
+the pulse transversely (replicate_yz), where they wrap alike.  I_S is
+discontinuous on its spheres (R = L, R = r(t), ...), which nodes can lie on:
+when the origin is a node, a node's coordinate is its integer offset from
+the origin times the spacing, so every grid with that spacing decides those
+nodes alike (x_min + i dx rounds differently from grid to grid).
 """
 import math
 
@@ -50,19 +55,31 @@ def window_nodes(grid, win):
         ic = math.floor((c - lo) / d + 0.5)
         idx.append(ic + np.arange(w) - w // 2)
     I, J, K = idx
-    if J.min() < 0 or J.max() >= grid["ny"] or K.min() < 0 or K.max() >= grid["nz"]:
+    if not grid.get("replicate_yz") and (J.min() < 0 or J.max() >= grid["ny"] or K.min() < 0
+                                         or K.max() >= grid["nz"]):
         raise ValueError("window leaves the transverse extent of the grid")
     return I, J, K
+
+
+def node_coords(I, lo, d):
+    """Coordinates of nodes I along an axis starting at lo with spacing d:
+    integer offsets from the origin node times d when the origin is a node."""
+    o = lo / d
+    r = round(o)
+    if abs(o - r) <= 1e-6:
+        return (np.asarray(I, dtype=np.int64) + r).astype(np.float64) * d
+    return lo + np.asarray(I) * d
 
 
 def readout(fields6, grid, win, t, R_min, R_max):
     """Focal window (6, wz, wy, wx) cut out of layer fields (6, nz, ny, nx)."""
     I, J, K = window_nodes(grid, win)
     ix = np.mod(I, grid["nx"])                                   # T on nodes
-    x = grid["x_min"] + I * grid["dx"]
-    y = grid["y_min"] + J * grid["dy"]
-    z = grid["z_min"] + K * grid["dz"]
+    x = node_coords(I, grid["x_min"], grid["dx"])
+    y = node_coords(J, grid["y_min"], grid["dy"])
+    z = node_coords(K, grid["z_min"], grid["dz"])
     mask = indicator(x[None, None, :], y[None, :, None], z[:, None, None],
                      t, R_min, R_max)
-    sub = fields6[:, K][:, :, J][:, :, :, ix]
+    jy, kz = (np.mod(J, grid["ny"]), np.mod(K, grid["nz"])) if grid.get("replicate_yz") else (J, K)
+    sub = fields6[:, kz][:, :, jy][:, :, :, ix]
     return sub * mask[None]

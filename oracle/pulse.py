@@ -271,7 +271,10 @@ def preimage_range(grid, g):
 
 def init_fields_at(p, grid, iz, iy, ix):
     """E, B at the layer nodes (iz, iy, ix): sum over preimages x + n D of
-    the pulse (Eq. (13) inverted; preimages superpose).  Returns two (3, npts) arrays."""
+    the pulse (Eq. (13) inverted; preimages superpose).  With
+    grid["replicate_yz"] the transverse periods Dy = ny dy, Dz = nz dz map
+    the pulse too (duplication along y and z, Sec. II.C closing remarks):
+    the sum also runs over y + m Dy, z + l Dz.  Returns two (3, npts) arrays."""
     g = geometry(p)
     gnorm = spectral_norm(p) if p["envelope"] == "spectral" else None
     D = grid["nx"] * grid["dx"]
@@ -281,13 +284,24 @@ def init_fields_at(p, grid, iz, iy, ix):
     E = np.zeros((3,) + xt.shape)
     B = np.zeros((3,) + xt.shape)
     nlo, nhi = preimage_range(grid, g)
-    for n in range(nlo, nhi + 1):
-        x = xt + n * D
-        if np.all(np.abs(x) > g["R_max"]):
+    shifts = [(0.0, 0.0)]
+    if grid.get("replicate_yz"):
+        Dy, Dz = grid["ny"] * grid["dy"], grid["nz"] * grid["dz"]
+        R = g["R_max"]
+        ms = range(math.floor((-R - y.max()) / Dy) - 1, math.ceil((R - y.min()) / Dy) + 2)
+        ls = range(math.floor((-R - z.max()) / Dz) - 1, math.ceil((R - z.min()) / Dz) + 2)
+        shifts = [(m * Dy, l * Dz) for l in ls for m in ms]
+    for sy, sz in shifts:
+        ys, zs = y + sy, z + sz
+        if np.all(ys * ys + zs * zs > g["R_max"] ** 2):
             continue
-        e, b = fields_at(x, y, z, p, g, gnorm)
-        E += e
-        B += b
+        for n in range(nlo, nhi + 1):
+            x = xt + n * D
+            if np.all(np.abs(x) > g["R_max"]):
+                continue
+            e, b = fields_at(x, ys, zs, p, g, gnorm)
+            E += e
+            B += b
     return E, B
 
 

@@ -172,7 +172,7 @@ void batch_free(tf_batch* b) {
 
 bool same_grid(const tf_grid& a, const tf_grid& b) {
     return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.dx == b.dx && a.dy == b.dy && a.dz == b.dz &&
-           a.x_min == b.x_min && a.y_min == b.y_min && a.z_min == b.z_min;
+           a.x_min == b.x_min && a.y_min == b.y_min && a.z_min == b.z_min && a.replicate_yz == b.replicate_yz;
 }
 
 // Window node indices of instance i (host); false if outside the grid.
@@ -181,7 +181,7 @@ bool window_origin(const tf_grid& g, const tf_window& w, long& ic, long& jc, lon
     jc = (long)std::floor((w.cy - g.y_min) / g.dy + 0.5);
     kc = (long)std::floor((w.cz - g.z_min) / g.dz + 0.5);
     const long j0 = jc - w.wy / 2, k0 = kc - w.wz / 2;
-    return j0 >= 0 && j0 + w.wy <= g.ny && k0 >= 0 && k0 + w.wz <= g.nz;
+    return g.replicate_yz || (j0 >= 0 && j0 + w.wy <= g.ny && k0 >= 0 && k0 + w.wz <= g.nz);
 }
 
 template <typename T>

@@ -233,6 +233,7 @@ inline GridDev grid_dev(const tf_grid& s) {
     g.nx = s.nx; g.ny = s.ny; g.nz = s.nz;
     g.dx = s.dx; g.dy = s.dy; g.dz = s.dz;
     g.x_min = s.x_min; g.y_min = s.y_min; g.z_min = s.z_min;
+    g.rep_yz = s.replicate_yz;
     return g;
 }
 
@@ -257,6 +258,7 @@ inline tf_status validate_grid(const tf_grid* grid) {
         return fail(TF_EINVAL, "spacings must be finite and > 0");
     if (!std::isfinite(grid->x_min) || !std::isfinite(grid->y_min) || !std::isfinite(grid->z_min))
         return fail(TF_EINVAL, "grid origin must be finite");
+    if (grid->replicate_yz != 0 && grid->replicate_yz != 1) return fail(TF_EINVAL, "replicate_yz must be 0 or 1");
     for (int n : {grid->nx, grid->ny, grid->nz})
         if (!length_ok(n))
             return fail(TF_EUNSUPPORTED, "axis length " + std::to_string(n) +

@@ -85,7 +85,9 @@ __device__ void add_pulse(double x, double y, double z, const PulseDev& p, doubl
 }
 
 // One thread per layer node: sum of the pulse over the preimages x + n D,
-// n ascending (Eq. (13) inverted; overlapping replicas superpose).
+// n ascending (Eq. (13) inverted; overlapping replicas superpose); with
+// transverse replication also over y + m Dy, z + l Dz (l, then m ascending
+// outside the x preimages).
 template <typename T>
 __global__ __launch_bounds__(256) void k_init_map(T* __restrict__ state, GridDev g, PulseDev p) {
     const long cells = (long)g.nx * g.ny * g.nz;
@@ -100,12 +102,22 @@ __global__ __launch_bounds__(256) void k_init_map(T* __restrict__ state, GridDev
     const double z = g.z_min + k * g.dz;
     const double Rmax = p.R0 + 0.5 * p.L;
     double e[3] = {0.0, 0.0, 0.0}, b[3] = {0.0, 0.0, 0.0};
-    const double tr2 = y * y + z * z;
-    if (tr2 <= Rmax * Rmax) {
-        const long n0 = (long)floor((-Rmax - xt) / D) - 1;
-        const long n1 = (long)ceil((Rmax - xt) / D) + 1;
-        for (long n = n0; n <= n1; ++n) add_pulse(xt + n * D, y, z, p, e, b);
+    const long n0 = (long)floor((-Rmax - xt) / D) - 1;
+    const long n1 = (long)ceil((Rmax - xt) / D) + 1;
+    long m0 = 0, m1 = 0, l0 = 0, l1 = 0;
+    const double Dy = g.ny * g.dy, Dz = g.nz * g.dz;
+    if (g.rep_yz) {
+        m0 = (long)floor((-Rmax - y) / Dy) - 1;
+        m1 = (long)ceil((Rmax - y) / Dy) + 1;
+        l0 = (long)floor((-Rmax - z) / Dz) - 1;
+        l1 = (long)ceil((Rmax - z) / Dz) + 1;
     }
+    for (long l = l0; l <= l1; ++l)
+        for (long m = m0; m <= m1; ++m) {
+            const double yy = g.rep_yz ? y + m * Dy : y, zz = g.rep_yz ? z + l * Dz : z;
+            if (yy * yy + zz * zz <= Rmax * Rmax)
+                for (long n = n0; n <= n1; ++n) add_pulse(xt + n * D, yy, zz, p, e, b);
+        }
     state[0 * cells + id] = T(e[0]);
     state[1 * cells + id] = T(e[1]);
     state[2 * cells + id] = T(e[2]);
@@ -115,6 +127,16 @@ __global__ __launch_bounds__(256) void k_init_map(T* __restrict__ state, GridDev
 }
 
 // ---------------------------------------------------------------- cut-out
+// Coordinate of node I along an axis.  When the origin is a node (lo / d an
+// integer), the coordinate is the node's integer offset from the origin
+// times d, so grids that share the spacing give the very same value to the
+// same point, and the cut-out of Eq. (15) decides nodes on its spheres
+// (R = L, R = r(t), ...) alike in every such grid.
+__device__ double node_coord(long I, double lo, double d) {
+    const double o = lo / d, r = rint(o);
+    return fabs(o - r) <= 1e-6 ? (double)(I + (long)r) * d : lo + I * d;
+}
+
 // I_S(t)(R) of Eq. (15), third case read as "x >= 0 and R > r(t)".
 __device__ bool cutout_keep(double x, double y, double z, double t, double Rmin, double Rmax) {
     const double R = sqrt(x * x + y * y + z * z);
@@ -136,10 +158,17 @@ __global__ __launch_bounds__(256) void k_readout(const T* __restrict__ state, T*
     const long I = ic + a - wx / 2, J = jc + bj - wy / 2, K = kc + ck - wz / 2;
     long ix = I % g.nx;
     if (ix < 0) ix += g.nx;
-    const double x = g.x_min + I * g.dx, y = g.y_min + J * g.dy, z = g.z_min + K * g.dz;
+    long jy = J, kz = K;
+    if (g.rep_yz) {
+        jy = J % g.ny;
+        if (jy < 0) jy += g.ny;
+        kz = K % g.nz;
+        if (kz < 0) kz += g.nz;
+    }
+    const double x = node_coord(I, g.x_min, g.dx), y = node_coord(J, g.y_min, g.dy), z = node_coord(K, g.z_min, g.dz);
     const bool keep = cutout_keep(x, y, z, t, Rmin, Rmax);
     const long cells = (long)g.nx * g.ny * g.nz;
-    const long src = (K * g.ny + J) * g.nx + ix;
+    const long src = (kz * g.ny + jy) * g.nx + ix;
     for (int c = 0; c < 6; ++c) out[c * wn + id] = keep ? state[c * cells + src] : T(0);
 }
 

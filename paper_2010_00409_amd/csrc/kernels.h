@@ -88,6 +88,7 @@ struct PulseDev {
 struct GridDev {
     int nx, ny, nz;
     double dx, dy, dz, x_min, y_min, z_min;
+    int rep_yz;                   // y and z are periods of the mapping too
 };
 
 template <typename T> hipError_t launch_init_map(T* state, const GridDev& g, const PulseDev& p,

@@ -502,7 +502,7 @@ tf_status tf_read_focal(tf_solver* s, const tf_window* w, void* dst, int32_t dst
     const long jc = (long)std::floor((w->cy - g.y_min) / g.dy + 0.5);
     const long kc = (long)std::floor((w->cz - g.z_min) / g.dz + 0.5);
     const long j0 = jc - w->wy / 2, j1 = j0 + w->wy - 1, k0 = kc - w->wz / 2, k1 = k0 + w->wz - 1;
-    if (j0 < 0 || j1 >= g.ny || k0 < 0 || k1 >= g.nz)
+    if (!g.replicate_yz && (j0 < 0 || j1 >= g.ny || k0 < 0 || k1 >= g.nz))
         return fail(TF_EINVAL, "window leaves the transverse extent of the grid");
     const size_t bytes = 6 * (size_t)w->wx * w->wy * w->wz * s->esize;
     void* out = dst;

@@ -33,7 +33,7 @@ class TfError(RuntimeError):
 
 class tf_grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("reserved", ctypes.c_int32),
+                ("replicate_yz", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
                 ("x_min", ctypes.c_double), ("y_min", ctypes.c_double), ("z_min", ctypes.c_double)]
 
@@ -159,12 +159,16 @@ def _check(status):
 def grid_struct(g):
     if isinstance(g, tf_grid):
         return g
-    return tf_grid(int(g["nx"]), int(g["ny"]), int(g["nz"]), 0, float(g["dx"]), float(g["dy"]),
+    return tf_grid(int(g["nx"]), int(g["ny"]), int(g["nz"]), int(g.get("replicate_yz", 0)), float(g["dx"]),
+                   float(g["dy"]),
                    float(g["dz"]), float(g["x_min"]), float(g["y_min"]), float(g["z_min"]))
 
 
 def grid_dict(s):
-    return {k: getattr(s, k) for k in ("nx", "ny", "nz", "dx", "dy", "dz", "x_min", "y_min", "z_min")}
+    d = {k: getattr(s, k) for k in ("nx", "ny", "nz", "dx", "dy", "dz", "x_min", "y_min", "z_min")}
+    if s.replicate_yz:
+        d["replicate_yz"] = 1
+    return d
 
 
 def pulse_struct(p):

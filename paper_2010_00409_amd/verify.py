@@ -1,5 +1,6 @@
-"""The method against direct computation (Sec. III.A) and the paper's
-focusing examples (Sec. III.B.1-2), on the library.
+"""The method against direct computation (Sec. III.A), the paper's focusing
+examples (Sec. III.B.1-2) and the transverse duplication it proposes
+(Sec. II.C, closing remarks), on the library.
 
 The paper verifies the mapping on its most demanding case: a flat-top pulse
 of f-number 0.3 (opening angle about 1 rad), length L = 2 wavelengths, edge
@@ -177,7 +178,7 @@ def gaussian_beam_vs_paraxial(f_numbers, n=512, side=40.0, window=48, span=1.0, 
 
 
 # ---------------------------------------------------------------- Sec. III.B.2
-def flattop_peak_vs_f(f_numbers, nx=128, nt=1024, window=(64, 48, 48), t_span=(-3.0, 6.0), dt=1.0 / 32,
+def flattop_peak_vs_f(f_numbers, nx=128, nt=1024, window=(64, 48, 48), t_span=(-10.0, 4.0), dt=1.0 / 32,
                       precision="f32", pulse=None):
     """Peak cycle-averaged intensity of the flat-top pulse of Sec. III.A
     (L = 2, eps = 0.1, R0 = 16, P0 = 1) and where and when it is reached, for
@@ -197,3 +198,31 @@ def flattop_peak_vs_f(f_numbers, nx=128, nt=1024, window=(64, 48, 48), t_span=(-
         rows.append(dict(f_number=float(f), theta=tf.tf_pulse_geometry(p)["theta"], peak_intensity=intensity(e2),
                          t_peak=t, x_peak=pos[0], peak_position=list(pos)))
     return rows
+
+
+# ---------------------------------------------------------------- Sec. II.C, closing remarks
+def transverse_duplication(boxes, nx=128, points_per_lambda=12, full=512, window=64, precision="f32",
+                           pulse=None, reps=3):
+    """The layer shrunk transversely as well: the pulse is replicated along y
+    and z with periods ny dy, nz dz (solver periodicity and linearity), so a
+    box of n_t x n_t transverse nodes replaces the full_ x full_ one.  Error
+    of each box's focal window (one exact step to the focus, through the
+    cut-out) against the full transverse layer of the same period, with the
+    time and memory the box saves."""
+    p = dict(VERIFY_PULSE if pulse is None else pulse)
+    d = float(p["wavelength"]) / points_per_lambda
+    win = dict(wx=window, wy=window, wz=window, cx=0.0, cy=0.0, cz=0.0)
+    ref_grid = tf.tf_layer_grid(p, (nx, full, full), (d, d, d))
+    ref, t_ref = focal_run(ref_grid, p, win, precision, reps)
+    peak = float(ref.abs().max())
+    rows = []
+    for nt in boxes:
+        g = dict(tf.tf_layer_grid(p, (nx, nt, nt), (d, d, d)), replicate_yz=1)
+        got, t = focal_run(g, p, win, precision, reps)
+        diff = got.double() - ref.double()
+        rows.append(dict(n_t=nt, period=nt * d, period_over_L=nt * d / p["L"],
+                         max_err_over_peak=float(diff.abs().max()) / peak,
+                         rel_l2=float(diff.norm() / ref.double().norm()), seconds=t, time_ratio=t_ref / t,
+                         memory_ratio=device_bytes(ref_grid, precision) / device_bytes(g, precision)))
+        del got, diff
+    return dict(pulse=p, precision=precision, nx=nx, full=full, reference_seconds=t_ref, peak=peak, boxes=rows)

@@ -144,6 +144,28 @@ def test_readout_matches_oracle_bitwise_f64():
         assert np.array_equal(out, ref)
 
 
+def test_transverse_replication_init_and_wrapped_window_match_oracle():
+    """Duplication along y and z (Sec. II.C closing remarks), float64: the
+    replicated init of a small transverse box and a focal window wider than
+    the box (wrapping in y and z) against the oracle."""
+    p = configs.pulse(envelope="spectral", bandwidth=0.4, R0=4.0, L=2.0, theta=0.8, eps=0.1, nfreq=64)
+    d = 0.25
+    g = dict(pulse.layer_grid(p, (16, 16, 24), (d, d, d)), replicate_yz=1)
+    with tf.Solver(g, "f64") as s:
+        s.set_pulse(p)
+        st = np.empty(s.shape)
+        s.get_fields(st)
+        win = dict(wx=8, wy=24, wz=40, cx=0.0, cy=0.3, cz=-0.2)
+        w = np.empty((6, 40, 24, 8))
+        s.read_focal(win, w)
+    E, B = pulse.init_fields(p, g)
+    ref = np.concatenate([E, B])
+    assert np.abs(ref).max() > 0.1
+    assert rel(st, ref) <= F64_TOL
+    geo = pulse.geometry(p)
+    assert np.array_equal(w, mapping.readout(st, g, win, 0.0, geo["R_min"], geo["R_max"]))
+
+
 def test_readout_rejects_window_outside_grid():
     g = configs.cube_grid(32, 0.25)
     with tf.Solver(g, "f32") as s:

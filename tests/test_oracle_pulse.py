@@ -286,6 +286,29 @@ def test_indicator_cases():
     assert ind(10.0, 26.0) == 1.0 and ind(-10.0, 26.0) == 0.0 and ind(8.9, 26.0) == 0.0
 
 
+def test_cutout_decides_nodes_on_its_spheres_alike_in_every_grid():
+    """At the focus (t = R0) the cut-out keeps R <= L for x < 0 and
+    R <= r(t) = L / 2 for x >= 0; with dx = lambda / 12 and L = 2 the axis
+    nodes at x = -24 dx and x = +12 dx lie on those spheres.  A cube centred
+    on the origin and layers of every period must read the same window
+    through the same cut-out (node coordinates are integer offsets from the
+    origin node times the spacing), and those nodes are kept (R = L and
+    R = r exactly)."""
+    p = configs.pulse(envelope="cos2", R0=16.0, L=2.0, f_number=0.3, eps=0.1)
+    g = pulse.geometry(p)
+    d = 1 / 12
+    win = dict(wx=64, wy=64, wz=64, cx=0.0, cy=0.0, cz=0.0)
+    cube = configs.cube_grid(64, d)
+    ones = np.ones((6, 64, 64, 64))
+    ref = mapping.readout(ones, cube, win, p["R0"], g["R_min"], g["R_max"])
+    assert ref[0, 32, 32, 32 - 24] == 1.0 and ref[0, 32, 32, 32 - 25] == 0.0
+    assert ref[0, 32, 32, 32 + 12] == 1.0 and ref[0, 32, 32, 32 + 13] == 0.0
+    for nx in (48, 64, 96, 128, 192):
+        grid = pulse.layer_grid(p, (nx, 64, 64), (d, d, d))
+        out = mapping.readout(np.ones((6, 64, 64, nx)), grid, win, p["R0"], g["R_min"], g["R_max"])
+        assert np.array_equal(out, ref), nx
+
+
 def test_readout_at_start_recovers_the_unmapped_pulse():
     p = configs.pulse(envelope="cos2", R0=6.0, L=2.0, theta=1.0)
     g = pulse.geometry(p)
@@ -331,3 +354,42 @@ def test_P14_mapped_focus_converges_to_direct_computation():
         errs.append(np.abs(focal(grid) - ref).max() / peak)
     assert errs[0] > errs[1] > errs[2]
     assert errs[1] < 0.01 and errs[2] < 0.006
+
+
+def _dup_case():
+    p = configs.pulse(envelope="cos2", R0=4.0, L=2.0, theta=0.8, eps=0.1)
+    d = 0.25
+    big = pulse.layer_grid(p, (16, 48, 48), (d, d, d))        # holds the pulse: |y|, |z| < 6
+    small = dict(pulse.layer_grid(p, (16, 16, 16), (d, d, d)), replicate_yz=1)
+    return p, d, big, small
+
+
+def test_transverse_replication_folds_the_full_layer():
+    """Duplication along y and z (Sec. II.C closing remarks): the replicated
+    init of a 16 x 16 transverse box equals the init of a box holding the
+    whole pulse folded onto it (block rows j, j + 16, j + 32 summed), and on
+    the box holding the pulse replication adds nothing."""
+    p, d, big, small = _dup_case()
+    Eb, Bb = pulse.init_fields(p, big)
+    Es, Bs = pulse.init_fields(p, small)
+    fb = np.concatenate([Eb, Bb])
+    fold = sum(fb[:, 16 * l:16 * (l + 1), 16 * m:16 * (m + 1), :] for l in range(3) for m in range(3))
+    got = np.concatenate([Es, Bs])
+    assert np.abs(fb).max() > 0.1
+    assert np.abs(got - fold).max() <= 1e-12 * np.abs(fold).max()
+    Er, Br = pulse.init_fields(p, dict(big, replicate_yz=1))
+    assert np.array_equal(Er, Eb) and np.array_equal(Br, Bb)
+
+
+def test_transverse_replication_wraps_the_window():
+    """A window wider than the replicated box reads the periodic state: it
+    equals the window of the state tiled three times along y and z."""
+    p, d, big, small = _dup_case()
+    g = pulse.geometry(p)
+    st = np.random.default_rng(3).standard_normal((6, 16, 16, 16))
+    win = dict(wx=8, wy=24, wz=20, cx=0.0, cy=0.3, cz=-0.2)
+    out = mapping.readout(st, small, win, 1.0, g["R_min"], g["R_max"])
+    tiled = np.tile(st, (1, 3, 3, 1))
+    tg = dict(small, replicate_yz=0, ny=48, nz=48, y_min=small["y_min"] - 16 * d, z_min=small["z_min"] - 16 * d)
+    ref = mapping.readout(tiled, tg, win, 1.0, g["R_min"], g["R_max"])
+    assert np.array_equal(out, ref)

@@ -3,6 +3,8 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-surrogate]
     python bench.py --workload c4          # batched sweep of 64 uneven grids
     python bench.py --workload surrogate   # the surrogate section alone
+    python bench.py --workload verify|duplicate|paraxial|flattop|perturbed
+                                           # the paper's verification and focusing examples
 
 Workload (C3): a 512^3 float32 periodic layer, dx = lambda/12, a two-octave
 single-cycle spectral pulse (f = 0.5, radial polarisation) put on the
@@ -48,7 +50,7 @@ def parse():
     ap.add_argument("--psatd-steps", type=int, default=None, help="override steps per run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "surrogate", "verify", "paraxial",
-                                                         "flattop", "duplicate"])
+                                                         "flattop", "perturbed", "duplicate"])
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate timing on c3/c2")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
@@ -296,7 +298,8 @@ def bench_examples(args):
     intensity at the focus against the paraxial I0 = 2 P0 / (pi w0^2) for
     f = 0.25 ... 2, 512^3 nodes over 40 lambda) or the flat-top pulse of
     Sec. III.B.2 (peak intensity and where it is reached against f, D = 2 L
-    on 128 x 1024 x 1024 nodes)."""
+    on 128 x 1024 x 1024 nodes), or the same pulse at f = 1 under random
+    wavefront perturbations (Sec. III.B.3)."""
     import torch
     from paper_2010_00409_amd import verify
 
@@ -309,6 +312,18 @@ def bench_examples(args):
                     value=rows[-1]["ratio"], unit="ratio",
                     config={"workload": "Sec. III.B.1: Gaussian envelope n = 4, Gaussian aperture tan theta0 = 1/(2f), "
                                         "R0 = 20, P0 = 1, 512^3 nodes over 40 lambda, float32, time scan R0 +- 1"})
+    elif args.workload == "perturbed":
+        res = verify.perturbed_focus((0.25, 0.5, 1.0, 1.5, 2.0, 3.0), runs=20)
+        rows = res.pop("levels")
+        head = dict(metric="flat-top pulse at f = 1: mean peak intensity / unperturbed under eps_phi = 1 "
+                           "wavefront perturbations",
+                    value=[r for r in rows if r["eps_phi"] == 1.0][0]["ratio_mean"], unit="ratio",
+                    config={"workload": "Sec. III.B.3: Sec. III.A pulse (L = 2, eps = 0.1, R0 = 16) at f = 1, "
+                                        f"{res['nbumps']} Gaussian phase bumps of width 0.3 theta, amplitudes "
+                                        "uniform in +-eps_phi, 20 draws per level, D = 2 L on 96 x 512 x 512 "
+                                        "nodes, float32, window following the pulse"},
+                    unperturbed={k: res[k] for k in ("theta", "nbumps", "peak_intensity", "t_peak", "x_peak")},
+                    samples=res["samples"])
     else:
         fs = fs + (3.0,)
         rows = verify.flattop_peak_vs_f(fs)
@@ -333,7 +348,7 @@ def main():
     if args.workload in ("verify", "duplicate"):
         bench_verify(args)
         return
-    if args.workload in ("paraxial", "flattop"):
+    if args.workload in ("paraxial", "flattop", "perturbed"):
         bench_examples(args)
         return
     if args.workload == "surrogate":

@@ -109,6 +109,15 @@ typedef struct {
     double pol_angle, ellipticity;
     double cep, gdd, tod;  /* carrier-envelope phase, chirp (time units^2, ^3)   */
     double bandwidth;      /* TF_ENV_SPECTRAL: relative 1/e half-width delta      */
+    int32_t nbumps;        /* wavefront phase perturbation (Sec. III.B.3): number
+                              of Gaussian bumps, 0..1024                           */
+    int32_t reserved;
+    const double* bumps;   /* host, nbumps x {ay, az, amplitude, width}: the
+                              direction of a point, alpha (y, z) / rho, gets the
+                              phase sum_i amplitude_i exp(-|(ay, az) - (ay_i,
+                              az_i)|^2 / width_i^2) added to its carrier phase
+                              (as cep is); copied by tf_set_pulse /
+                              tf_batch_create, not kept                            */
 } tf_pulse;
 
 /* Geometry derived from a pulse by tf_pulse_geometry / tf_set_pulse. */

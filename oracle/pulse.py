@@ -213,8 +213,26 @@ def phasor_weights(p, nbasis):
     return np.array([za.real, -za.imag, zb.real, -zb.imag]) / gn
 
 
+def bump_phase(alpha, y, z, p):
+    """Wavefront phase perturbation of Sec. III.B.3 at directions given by
+    alpha (angle from -x) and the transverse position (y, z): a sum of
+    Gaussian bumps exp(-|a - a_i|^2 / w_i^2) times amplitude_i over the
+    angular position a = alpha (y, z) / rho (0 on the axis)."""
+    bumps = p.get("bumps") or []
+    rho = np.sqrt(y * y + z * z)
+    safe = np.where(rho > 0.0, rho, 1.0)
+    ay = np.where(rho > 0.0, alpha * y / safe, 0.0)
+    az = np.where(rho > 0.0, alpha * z / safe, 0.0)
+    ph = np.zeros(np.shape(alpha))
+    for by, bz, amp, w in bumps:
+        ph = ph + amp * np.exp(-((ay - by) ** 2 + (az - bz) ** 2) / (w * w))
+    return ph
+
+
 def fields_at(x, y, z, p, g, gnorm=None):
-    """E, B (each a (3, ...) array) of the unmapped pulse at points."""
+    """E, B (each a (3, ...) array) of the unmapped pulse at points.  A
+    wavefront phase perturbation (p["bumps"]) adds to every polarisation
+    part's carrier phase, as the CEP does."""
     x, y, z = (np.asarray(v, dtype=np.float64) for v in (x, y, z))
     x, y, z = np.broadcast_arrays(x, y, z)
     shape = x.shape
@@ -233,8 +251,9 @@ def fields_at(x, y, z, p, g, gnorm=None):
     if p["envelope"] == "spectral" and gnorm is None:
         gnorm = spectral_norm(p)
     ts = u_ts(al, p, g)
+    dph = bump_phase(al, ys, zs, p)
     for amp, d, ph in pol_parts(p):
-        u = g["A"] / Rs * u_l(ze, p, p["cep"] + ph, gnorm) * ts
+        u = g["A"] / Rs * u_l(ze, p, p["cep"] + ph + dph, gnorm) * ts
         # s1 ~ d x R, s0 ~ R x (d x R)
         c1 = (d[1] * zs - d[2] * ys, d[2] * xs - d[0] * zs, d[0] * ys - d[1] * xs)
         n1 = np.sqrt(c1[0] * c1[0] + c1[1] * c1[1] + c1[2] * c1[2])

@@ -357,22 +357,23 @@ tf_status tf_batch_create(const tf_grid* grids, const tf_pulse* pulses, int32_t 
         st = fail(TF_EDEVICE, "hipStreamCreate failed");
     for (int i = 0; i < n && st == TF_OK; ++i) {
         b->pdev[i] = pulse_dev(&pulses[i], b->infos[i]);
-        if (pulses[i].envelope == TF_ENV_SPECTRAL) {
-            std::vector<double> tab;
-            double gnorm = 0.0;
-            spectral_table(&pulses[i], tab, gnorm);
-            if (!(gnorm > 0.0) || tab.empty()) {
-                st = fail(TF_EINVAL, "instance " + std::to_string(i) + ": spectral pulse has no samples above w = 0");
-                break;
-            }
-            const std::vector<double> dtab = spectral_device_table(&pulses[i], tab);
-            st = alloc(&b->tabs[i], dtab.size() * sizeof(double));
-            if (st == TF_OK && hipMemcpy(b->tabs[i], dtab.data(), dtab.size() * sizeof(double), hipMemcpyHostToDevice) !=
-                                   hipSuccess)
-                st = fail(TF_EDEVICE, "spectral table upload failed");
-            b->pdev[i].nfreq = (int)(tab.size() / 3);
-            b->pdev[i].spec = static_cast<const double*>(b->tabs[i]);
-            b->pdev[i].gnorm = gnorm;
+        std::vector<double> all;
+        size_t spec_len = 0;
+        double gnorm = 1.0;
+        int nfreq = 0;
+        st = pulse_tables(&pulses[i], all, spec_len, gnorm, nfreq);
+        if (st != TF_OK) {
+            st = fail(st, "instance " + std::to_string(i) + ": " + last_error());
+            break;
+        }
+        if (!all.empty()) {
+            st = alloc(&b->tabs[i], all.size() * sizeof(double));
+            if (st == TF_OK &&
+                hipMemcpy(b->tabs[i], all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+                st = fail(TF_EDEVICE, "pulse table upload failed");
+            if (st == TF_OK)
+                pulse_dev_tables(b->pdev[i], &pulses[i], static_cast<const double*>(b->tabs[i]), spec_len, gnorm,
+                                 nfreq);
         }
     }
     if (st != TF_OK) {

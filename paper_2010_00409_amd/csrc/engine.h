@@ -79,6 +79,13 @@ inline tf_status validate_pulse(const tf_pulse* p) {
         return fail(TF_EINVAL, "phase/polarisation parameters must be finite");
     if (p->polarization == TF_POL_RADIAL && p->ellipticity != 0.0)
         return fail(TF_EINVAL, "radial polarisation takes no ellipticity");
+    if (p->nbumps < 0 || p->nbumps > 1024) return fail(TF_EINVAL, "nbumps must be in [0, 1024]");
+    if (p->nbumps > 0 && !p->bumps) return fail(TF_EINVAL, "bumps is NULL");
+    for (int i = 0; i < p->nbumps; ++i) {
+        const double* b = p->bumps + 4 * i;
+        if (!std::isfinite(b[0]) || !std::isfinite(b[1]) || !std::isfinite(b[2]) || !finite_pos(b[3]))
+            return fail(TF_EINVAL, "phase bumps need finite centres and amplitudes and widths > 0");
+    }
     return TF_OK;
 }
 
@@ -184,6 +191,40 @@ inline hipError_t upload_twiddles(void* dst, int n, int prec, hipStream_t st) {
     }
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(st);
+}
+
+// Host form of everything the device descriptor points to: the spectral
+// table (when the envelope is spectral) followed by the phase bumps.
+// spec_len receives the spectral part's length (0 without one); gnorm and
+// nfreq as the spectral table gives them.
+inline tf_status pulse_tables(const tf_pulse* pulse, std::vector<double>& all, size_t& spec_len, double& gnorm,
+                              int& nfreq) {
+    all.clear();
+    spec_len = 0;
+    gnorm = 1.0;
+    nfreq = 0;
+    if (pulse->envelope == TF_ENV_SPECTRAL) {
+        std::vector<double> tab;
+        spectral_table(pulse, tab, gnorm);
+        if (!(gnorm > 0.0) || tab.empty()) return fail(TF_EINVAL, "spectral pulse has no samples above w = 0");
+        all = spectral_device_table(pulse, tab);
+        spec_len = all.size();
+        nfreq = (int)(tab.size() / 3);
+    }
+    all.insert(all.end(), pulse->bumps, pulse->bumps + 4 * (size_t)pulse->nbumps);
+    return TF_OK;
+}
+
+// Points the descriptor at a device copy of pulse_tables' output.
+inline void pulse_dev_tables(PulseDev& p, const tf_pulse* pulse, const double* dev, size_t spec_len, double gnorm,
+                             int nfreq) {
+    if (pulse->envelope == TF_ENV_SPECTRAL) {
+        p.spec = dev;
+        p.nfreq = nfreq;
+        p.gnorm = gnorm;
+    }
+    p.nbumps = pulse->nbumps;
+    p.bumps = pulse->nbumps > 0 ? dev + spec_len : nullptr;
 }
 
 // Device pulse descriptor; the spectral table (nfreq x {w, a, phi}) must be

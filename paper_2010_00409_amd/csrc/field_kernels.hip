@@ -56,6 +56,20 @@ __device__ void spectral_sum(double zeta, const PulseDev& p, double& sr, double&
     si = pr * es + pim * ec;
 }
 
+// Wavefront phase of the direction (alpha, azimuth): a sum of Gaussian bumps
+// over the angular position (ay, az) = alpha (y, z) / rho (Sec. III.B.3).
+__device__ double bump_phase(double alpha, double y, double z, double rho, const PulseDev& p) {
+    const double ay = rho > 0.0 ? alpha * y / rho : 0.0;
+    const double az = rho > 0.0 ? alpha * z / rho : 0.0;
+    double ph = 0.0;
+    for (int i = 0; i < p.nbumps; ++i) {
+        const double* bp = p.bumps + 4 * i;
+        const double dy = ay - bp[0], dz = az - bp[1];
+        ph += bp[2] * exp(-(dy * dy + dz * dz) / (bp[3] * bp[3]));
+    }
+    return ph;
+}
+
 // Adds the unmapped pulse at physical point (x, y, z) to e, b.
 __device__ void add_pulse(double x, double y, double z, const PulseDev& p, double* e, double* b) {
     const double R = sqrt(x * x + y * y + z * z);
@@ -67,9 +81,14 @@ __device__ void add_pulse(double x, double y, double z, const PulseDev& p, doubl
     const double ts = u_ts(alpha, p);
     double sr = 0.0, si = 0.0;
     if (p.envelope == 2) spectral_sum(zeta, p, sr, si);     // shared by both polarisation parts
+    // the perturbation adds to every part's carrier phase, as the CEP does
+    const double dph = p.nbumps > 0 ? bump_phase(alpha, y, z, rho, p) : 0.0;
+    double cb = 1.0, sb = 0.0;
+    if (p.nbumps > 0 && p.envelope == 2) sincos(dph, &sb, &cb);
     for (int k = 0; k < p.nparts; ++k) {
-        const double ul = p.envelope == 2 ? (p.cph[k] * sr - p.sph[k] * si) / p.gnorm
-                                          : u_l_closed(zeta, p.cep + p.phase_off[k], p);
+        const double ul = p.envelope == 2
+                              ? ((p.cph[k] * cb - p.sph[k] * sb) * sr - (p.sph[k] * cb + p.cph[k] * sb) * si) / p.gnorm
+                              : u_l_closed(zeta, p.cep + p.phase_off[k] + dph, p);
         const double u = p.A / R * ul * ts;
         const double* d = p.d[k];
         // s1 ~ d x R, s0 ~ R x (d x R)

@@ -83,6 +83,9 @@ struct PulseDev {
     // spectral only: {w0, dw, then c_m = a_m exp(i phi_m) as re, im} for the
     // nfreq kept samples w_m = w0 + m dw
     const double* spec;
+    // wavefront phase bumps {ay, az, amplitude, width} (nbumps of them)
+    int nbumps;
+    const double* bumps;
 };
 
 struct GridDev {

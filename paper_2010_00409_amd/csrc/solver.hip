@@ -416,24 +416,23 @@ tf_status tf_set_pulse(tf_solver* s, const tf_pulse* pulse, tf_pulse_info* info)
     if (!(g.D > pulse->L)) return fail(TF_EDOMAIN, "layer period D = nx dx must exceed the pulse length L");
 
     tf::PulseDev p = pulse_dev(pulse, g);
-    if (pulse->envelope == TF_ENV_SPECTRAL) {
-        std::vector<double> tab;
-        double gnorm = 0.0;
-        spectral_table(pulse, tab, gnorm);
-        if (!(gnorm > 0.0) || tab.empty()) return fail(TF_EINVAL, "spectral pulse has no samples above w = 0");
+    std::vector<double> all;
+    size_t spec_len = 0;
+    double gnorm = 1.0;
+    int nfreq = 0;
+    st = pulse_tables(pulse, all, spec_len, gnorm, nfreq);
+    if (st != TF_OK) return st;
+    if (!all.empty()) {
         if (s->pulse_tab) {
             TF_HIP(hipStreamSynchronize(s->stream));
             TF_HIP(hipFree(s->pulse_tab));
             s->pulse_tab = nullptr;
         }
-        const std::vector<double> dtab = spectral_device_table(pulse, tab);
-        TF_HIP(hipMalloc(&s->pulse_tab, dtab.size() * sizeof(double)));
-        TF_HIP(hipMemcpyAsync(s->pulse_tab, dtab.data(), dtab.size() * sizeof(double), hipMemcpyHostToDevice,
+        TF_HIP(hipMalloc(&s->pulse_tab, all.size() * sizeof(double)));
+        TF_HIP(hipMemcpyAsync(s->pulse_tab, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice,
                               s->stream));
         TF_HIP(hipStreamSynchronize(s->stream));
-        p.nfreq = (int)(tab.size() / 3);
-        p.spec = static_cast<const double*>(s->pulse_tab);
-        p.gnorm = gnorm;
+        pulse_dev_tables(p, pulse, static_cast<const double*>(s->pulse_tab), spec_len, gnorm, nfreq);
     }
     tf::GridDev gd = grid_dev(s->grid);
     hipError_t e = timed(s, TF_PASS_INIT, [&] {

@@ -43,7 +43,9 @@ class tf_pulse(ctypes.Structure):
                 ("polarization", ctypes.c_int32), ("nfreq", ctypes.c_int32)] + \
                [(n, ctypes.c_double) for n in ("wavelength", "R0", "L", "ncycles", "f_number",
                                                  "theta", "eps", "P0", "pol_angle", "ellipticity",
-                                                 "cep", "gdd", "tod", "bandwidth")]
+                                                 "cep", "gdd", "tod", "bandwidth")] + \
+               [("nbumps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("bumps", ctypes.POINTER(ctypes.c_double))]
 
 
 class tf_pulse_info(ctypes.Structure):
@@ -182,6 +184,12 @@ def pulse_struct(p):
     for k in ("wavelength", "R0", "L", "ncycles", "f_number", "theta", "eps", "P0", "pol_angle",
               "ellipticity", "cep", "gdd", "tod", "bandwidth"):
         setattr(s, k, float(p.get(k, 0.0)))
+    bumps = p.get("bumps")
+    if bumps is not None and len(bumps):
+        arr = (ctypes.c_double * (4 * len(bumps)))(*[float(v) for b in bumps for v in b])
+        s._bumps_keepalive = arr               # the struct only points at it
+        s.nbumps = len(bumps)
+        s.bumps = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
     return s
 
 

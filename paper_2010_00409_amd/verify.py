@@ -226,3 +226,67 @@ def transverse_duplication(boxes, nx=128, points_per_lambda=12, full=512, window
                          memory_ratio=device_bytes(ref_grid, precision) / device_bytes(g, precision)))
         del got, diff
     return dict(pulse=p, precision=precision, nx=nx, full=full, reference_seconds=t_ref, peak=peak, boxes=rows)
+
+
+# ---------------------------------------------------------------- Sec. III.B.3
+def phase_bumps(theta, eps_phi, rng, width_frac=0.3):
+    """The wavefront perturbation of Sec. III.B.3: (2 theta / sigma)^2 = 44
+    Gaussian bumps of width sigma = 0.3 theta, centred uniformly over the
+    aperture disc of angular radius theta, amplitudes uniform in
+    [-eps_phi, eps_phi].  Returns [(ay, az, amplitude, width)]."""
+    sigma = width_frac * theta
+    n = int(round((2.0 * theta / sigma) ** 2))
+    r = theta * (rng.uniform(size=n) ** 0.5)
+    a = 2.0 * math.pi * rng.uniform(size=n)
+    amp = rng.uniform(-eps_phi, eps_phi, size=n)
+    return [(float(r[i] * math.cos(a[i])), float(r[i] * math.sin(a[i])), float(amp[i]), sigma) for i in range(n)]
+
+
+def phase_std(bumps, theta, n=201):
+    """Standard deviation of the perturbation phase over the aperture disc
+    (angular positions |a| <= theta, uniform weight)."""
+    import numpy as np
+    g = np.linspace(-theta, theta, n)
+    ay, az = np.meshgrid(g, g, indexing="ij")
+    inside = ay * ay + az * az <= theta * theta
+    ph = np.zeros_like(ay)
+    for by, bz, amp, w in bumps:
+        ph += amp * np.exp(-((ay - by) ** 2 + (az - bz) ** 2) / (w * w))
+    return float(ph[inside].std())
+
+
+def perturbed_focus(eps_values, runs=20, f_number=1.0, nx=96, nt=512, window=(64, 64, 64), t_span=(-2.5, 1.0),
+                    dt=1.0 / 32, precision="f32", seed=20100409):
+    """Peak cycle-averaged intensity at the focus of the flat-top pulse of
+    Sec. III.A (L = 2, eps = 0.1, R0 = 16) at f-number 1 under random
+    wavefront perturbations (Sec. III.B.3): for each level eps_phi, runs
+    independent draws of phase_bumps, each scanned from R0 + t_span[0] to
+    R0 + t_span[1] with the window following the pulse centre, in a D = 2 L
+    layer of nx x nt x nt nodes.  Each run is reported as the phase spread
+    sigma(phi) over the aperture and the peak intensity relative to the
+    unperturbed pulse's."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    base = dict(VERIFY_PULSE, f_number=float(f_number))
+    theta = tf.tf_pulse_geometry(base)["theta"]
+    d = 2.0 * base["L"] / nx
+    grid = tf.tf_layer_grid(base, (nx, nt, nt), (d, d, d))
+    win = dict(wx=window[0], wy=window[1], wz=window[2], cx=0.0, cy=0.0, cz=0.0)
+
+    def peak(p):
+        return intensity_scan(grid, p, win, p["R0"] + t_span[0], p["R0"] + t_span[1], dt, precision, follow=True)
+
+    e2_ref, t_ref, pos_ref = peak(base)
+    levels, samples = [], []
+    for eps in eps_values:
+        ratios, stds = [], []
+        for _ in range(runs):
+            bumps = phase_bumps(theta, eps, rng)
+            e2, _, _ = peak(dict(base, bumps=bumps))
+            stds.append(phase_std(bumps, theta))
+            ratios.append(e2 / e2_ref)
+            samples.append(dict(eps_phi=float(eps), phase_std=stds[-1], intensity_ratio=ratios[-1]))
+        levels.append(dict(eps_phi=float(eps), phase_std=float(np.mean(stds)), ratio_mean=float(np.mean(ratios)),
+                           ratio_std=float(np.std(ratios)), ratio_min=float(np.min(ratios)), runs=runs))
+    return dict(theta=theta, nbumps=len(phase_bumps(theta, 0.0, rng)), peak_intensity=intensity(e2_ref),
+                t_peak=t_ref, x_peak=pos_ref[0], levels=levels, samples=samples)

@@ -150,3 +150,16 @@ def test_fast_z_kernel_needs_its_strip_offsets_to_fit_32_bits(monkeypatch):
     assert (511 * 512 + 1) * rowb > 2 ** 32 >= (511 * 8 + 1) * rowb
     with pytest.raises(tf.TfError):
         tf.tf_kernel_plan(dict(wide, nx=100), "f32")
+
+
+def test_phase_bumps_are_validated_before_any_hip_call():
+    p = configs.pulse()
+    assert tf.tf_pulse_geometry(dict(p, bumps=[(0.0, 0.1, 0.5, 0.2)]))["theta"] > 0
+    for bad in ([(0.0, 0.1, 0.5, 0.0)], [(float("nan"), 0.1, 0.5, 0.2)]):
+        with pytest.raises(tf.TfError) as ei:
+            tf.tf_pulse_geometry(dict(p, bumps=bad))
+        assert ei.value.status == tf.TF_EINVAL
+    s = tf.pulse_struct(p)
+    s.nbumps = 3                                   # count without a table
+    with pytest.raises(tf.TfError):
+        tf.tf_pulse_geometry(s)

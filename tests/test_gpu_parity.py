@@ -166,6 +166,27 @@ def test_transverse_replication_init_and_wrapped_window_match_oracle():
     assert np.array_equal(w, mapping.readout(st, g, win, 0.0, geo["R_min"], geo["R_max"]))
 
 
+@pytest.mark.parametrize("envelope", ["cos2", "spectral"])
+def test_phase_perturbed_init_matches_oracle(envelope):
+    """Wavefront phase bumps (Sec. III.B.3) in the init, float64, against the
+    oracle: 44 bumps of width 0.3 theta over the aperture."""
+    from paper_2010_00409_amd import verify
+    p = configs.pulse(envelope=envelope, R0=4.0, L=2.0, f_number=1.0, eps=0.1, nfreq=64, cep=0.4)
+    th = pulse.geometry(p)["theta"]
+    p = dict(p, bumps=verify.phase_bumps(th, 0.8, np.random.default_rng(5)))
+    g = pulse.layer_grid(p, (24, 48, 48), (0.2, 0.2, 0.2))
+    with tf.Solver(g, "f64") as s:
+        s.set_pulse(p)
+        st = np.empty(s.shape)
+        s.get_fields(st)
+    E, B = pulse.init_fields(p, g)
+    ref = np.concatenate([E, B])
+    assert np.abs(ref).max() > 0.1
+    assert rel(st, ref) <= F64_TOL
+    E0, _ = pulse.init_fields(dict(p, bumps=None), g)
+    assert rel(E0, E) > 0.1                         # the perturbation changes the field
+
+
 def test_readout_rejects_window_outside_grid():
     g = configs.cube_grid(32, 0.25)
     with tf.Solver(g, "f32") as s:

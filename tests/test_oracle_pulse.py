@@ -393,3 +393,48 @@ def test_transverse_replication_wraps_the_window():
     tg = dict(small, replicate_yz=0, ny=48, nz=48, y_min=small["y_min"] - 16 * d, z_min=small["z_min"] - 16 * d)
     ref = mapping.readout(tiled, tg, win, 1.0, g["R_min"], g["R_max"])
     assert np.array_equal(out, ref)
+
+
+def test_phase_bump_closed_forms():
+    """A single bump of amplitude a and width w centred on the axis gives
+    phase a on the axis and a / e at angular distance w (Sec. III.B.3)."""
+    p = dict(configs.pulse(), bumps=[(0.0, 0.0, 0.7, 0.2)])
+    alpha = np.array([0.0, 0.2, 0.2])
+    y = np.array([0.0, 1.0, 0.0])
+    z = np.array([0.0, 0.0, -1.0])
+    ph = pulse.bump_phase(alpha, y, z, p)
+    assert np.allclose(ph, [0.7, 0.7 / np.e, 0.7 / np.e], rtol=1e-14)
+
+
+@pytest.mark.parametrize("envelope", ["cos2", "spectral"])
+def test_uniform_phase_bump_is_a_carrier_phase_shift(envelope):
+    """A bump far wider than the aperture adds one constant phase to every
+    direction: the perturbed pulse equals the pulse with that phase added to
+    its carrier-envelope phase (up to the spectral envelope's normalisation)."""
+    p = configs.pulse(envelope=envelope, R0=4.0, L=2.0, theta=0.8, eps=0.1, nfreq=64, cep=0.3)
+    grid = pulse.layer_grid(p, (16, 32, 32), (0.25, 0.25, 0.25))
+    E1, B1 = pulse.init_fields(dict(p, bumps=[(0.1, -0.2, 0.9, 1e6)]), grid)
+    E2, B2 = pulse.init_fields(dict(p, cep=1.2), grid)
+    if envelope == "spectral":
+        # the sampled-spectrum envelope is normalised by its peak at the
+        # pulse's own CEP; a bump leaves that normalisation alone
+        s = pulse.spectral_norm(dict(p, cep=1.2)) / pulse.spectral_norm(p)
+        E2, B2 = E2 * s, B2 * s
+    ref = np.abs(E2).max()
+    assert ref > 0.1
+    assert np.abs(E1 - E2).max() <= 1e-12 * ref and np.abs(B1 - B2).max() <= 1e-12 * ref
+
+
+def test_perturbation_draws_follow_the_paper():
+    """(2 theta / sigma)^2 = 44 bumps of width 0.3 theta inside the aperture
+    disc, amplitudes within +-eps_phi; the phase spread grows with eps_phi."""
+    from paper_2010_00409_amd import verify
+    rng = np.random.default_rng(0)
+    th = 0.4636
+    b = verify.phase_bumps(th, 0.5, rng)
+    assert len(b) == 44
+    assert all(by * by + bz * bz <= th * th + 1e-15 and abs(a) <= 0.5 and w == pytest.approx(0.3 * th)
+               for by, bz, a, w in b)
+    s1 = verify.phase_std(verify.phase_bumps(th, 0.2, np.random.default_rng(1)), th)
+    s2 = verify.phase_std(verify.phase_bumps(th, 0.8, np.random.default_rng(1)), th)
+    assert 0 < s1 < s2 and s2 == pytest.approx(4 * s1, rel=1e-12)

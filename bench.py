@@ -37,9 +37,18 @@ sys.path.insert(0, HERE)
 PEAK_HBM_GBS = 8000.0
 METRIC = "PSATD cell-updates/s + HBM GB/s at 512^3 FP32; surrogate speedup at 1e-2 err"
 PASS_BYTES_PER_CELL = {"f32": 48, "f64": 96}   # read + write of six components
-# kernel behind each pass of the float32 512^3 step (rocprofv3 short names)
-PASS_KERNEL = {"x_forward": "k_x_forward", "y_forward": "k_col_fast", "z_step": "k_z_fast",
-               "y_inverse": "k_col_fast", "x_inverse": "k_x_inverse"}
+
+
+def pass_kernels(plan, nz):
+    """Kernel (rocprofv3 short name) behind each pass of a step under a kernel
+    plan (row_block, fast, zvariant) with nz-point z columns."""
+    _, fast, zv = plan
+    if not fast:
+        z, col = "k_z", "k_col"
+    else:
+        z, col = ("k_z_wave" if zv >= 7 and nz == 512 else "k_z_fast"), "k_col_fast"
+    return {"x_forward": "k_x_forward", "y_forward": col, "z_step": z, "y_inverse": col,
+            "x_inverse": "k_x_inverse"}
 
 
 def parse():
@@ -58,12 +67,12 @@ def parse():
 
 
 def traffic_record(kernel):
-    """HBM bytes per launch measured by rocprofv3 counters for this kernel,
-    if recorded against the current kernel source (else None)."""
+    """HBM bytes per launch measured by rocprofv3 counters for this kernel
+    (short name), if recorded against the current kernel source (else None)."""
     path = os.path.join(HERE, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path)).get(PASS_KERNEL.get(kernel, kernel))
+    rec = json.load(open(path)).get(kernel)
     if not rec:
         return None
     from paper_2010_00409_amd.profile_summary import source_hash
@@ -430,7 +439,8 @@ def main():
     per_launch_s = dom_ms / dom_n / 1e3
     alg_bytes = PASS_BYTES_PER_CELL[prec] * cells
     achieved = alg_bytes / per_launch_s / 1e9
-    traffic = traffic_record(dom)
+    kernels = pass_kernels(tf.tf_kernel_plan(grid, prec), n[2])
+    traffic = traffic_record(kernels[dom])
     step_ms = sum(passes[k][0] for k in step_passes) / (steps * args.steps)
     hbm_gbs = PASS_BYTES_PER_CELL[prec] * len(step_passes) * cells / (step_ms / 1e3) / 1e9
 
@@ -458,7 +468,7 @@ def main():
         "hbm_gbs_pass_model": hbm_gbs,
         "ms_per_psatd_step": step_ms,
         "passes_ms_per_launch": {k: v[0] / v[1] for k, v in passes.items()},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
+        "roofline": {"bound": "hbm", "kernel": kernels[dom], "pass": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic, "alg_bytes_per_launch": alg_bytes},
         "focal_peak_abs": peak_field,

@@ -70,11 +70,20 @@ def test_traffic_record_needs_the_current_kernel_sources(tmp_path, monkeypatch):
     rec = {"k_z_fast": {"bytes_per_launch": 123.0, "source_sha256": ps.source_hash()}}
     (prof / "traffic.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "HERE", str(tmp_path))
-    assert bench.traffic_record("z_step") == 123.0
+    assert bench.traffic_record("k_z_fast") == 123.0
     rec["k_z_fast"]["source_sha256"] = "0" * 64
     (prof / "traffic.json").write_text(json.dumps(rec))
-    assert bench.traffic_record("z_step") is None
-    assert bench.traffic_record("x_forward") is None
+    assert bench.traffic_record("k_z_fast") is None
+    assert bench.traffic_record("k_x_forward") is None
+
+
+def test_pass_kernels_follow_the_plan():
+    assert bench.pass_kernels((8, True, 7), 512)["z_step"] == "k_z_wave"
+    assert bench.pass_kernels((8, True, 8), 512)["z_step"] == "k_z_wave"
+    assert bench.pass_kernels((8, True, 7), 256)["z_step"] == "k_z_fast"
+    assert bench.pass_kernels((8, True, 6), 512)["z_step"] == "k_z_fast"
+    k = bench.pass_kernels((8, False, 0), 512)
+    assert (k["z_step"], k["y_forward"], k["x_inverse"]) == ("k_z", "k_col", "k_x_inverse")
 
 
 def test_surrogate_bytes_grow_by_one_window_per_window():

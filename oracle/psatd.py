@@ -24,6 +24,20 @@ Readings where the paper is silent:
 
 Field arrays have shape (3, nz, ny, nx): component, z, y, x with x fastest,
 matching the library's [component][z][y][x] layout.
+
+With a current density j (``update_with_current``, ``step_fft_current``)
+the step is Eqs. (1)-(2) as printed, with j the coefficients of the current
+held over the step (j^{n+1/2}):
+
+    E' = C E + i S k_hat x B - (4 pi S / (kappa c)) j + (1 - C) k_hat (k_hat . E)
+         + 4 pi k_hat (k_hat . j) (S / (kappa c) - dt)
+    B' = C B - i S k_hat x E + 4 pi i ((1 - C) / (kappa c)) k_hat x j
+
+(CGS units).  The longitudinal part of E is kept and changes by
+-4 pi dt (k_hat . j), as Gauss's law with charge continuity requires.
+Reading: at kappa = 0 (k = 0, and modes whose only nonzero index is a
+Nyquist index) S / (kappa c) is taken at its limit dt and (1 - C) / (kappa c)
+at its limit 0, so a uniform current gives E' = E - 4 pi dt j, B' = B.
 """
 import numpy as np
 import scipy.fft
@@ -91,6 +105,51 @@ def update(Eh, Bh, k, dt, project_b=False, c=C_LIGHT):
     En = [C * ET[a] + 1j * S * kxB[a] for a in range(3)]
     Bn = [C * Bh[a] - 1j * S * kxE[a] for a in range(3)]
     return En, Bn
+
+
+def update_with_current(Eh, Bh, Jh, k, dt, project_b=False, c=C_LIGHT):
+    """Eqs. (1)-(2) applied to every mode: Eh, Bh, Jh sequences of 3 complex
+    arrays (Jh the current held over the step); k as in ``update``;
+    ``project_b`` first removes the longitudinal part of B (as ``update``).
+    Returns (E', B')."""
+    kx, ky, kz = k
+    kappa = np.sqrt(kx * kx + ky * ky + kz * kz)
+    nz = kappa > 0
+    safe = np.where(nz, kappa, 1.0)
+    inv = np.where(nz, 1.0 / safe, 0.0)
+    kh = (kx * inv, ky * inv, kz * inv)
+    C = np.cos(c * kappa * dt)
+    S = np.sin(c * kappa * dt)
+    s_over = np.where(nz, S / (safe * c), dt)                 # S / (kappa c) -> dt at kappa = 0
+    c_over = np.where(nz, (1.0 - C) / (safe * c), 0.0)        # (1 - C) / (kappa c) -> 0
+    if project_b:
+        kB = kh[0] * Bh[0] + kh[1] * Bh[1] + kh[2] * Bh[2]
+        Bh = [Bh[a] - kh[a] * kB for a in range(3)]
+    kE = kh[0] * Eh[0] + kh[1] * Eh[1] + kh[2] * Eh[2]
+    kJ = kh[0] * Jh[0] + kh[1] * Jh[1] + kh[2] * Jh[2]
+    kxB = _cross(kh, Bh)
+    kxE = _cross(kh, Eh)
+    kxJ = _cross(kh, Jh)
+    En = [C * Eh[a] + 1j * S * kxB[a] - 4.0 * np.pi * s_over * Jh[a] + (1.0 - C) * kh[a] * kE
+          + 4.0 * np.pi * kh[a] * kJ * (s_over - dt) for a in range(3)]
+    Bn = [C * Bh[a] - 1j * S * kxE[a] + 4.0j * np.pi * c_over * kxJ[a] for a in range(3)]
+    return En, Bn
+
+
+def step_fft_current(E, B, J, spacing, dt, project_b=False, workers=None):
+    """One step of Eqs. (1)-(2) with the real current density J (shape
+    (3, nz, ny, nx)) held over the step: rfftn -> update_with_current ->
+    irfftn, in float64."""
+    workers = workers or _workers()
+    shape = E.shape[1:]
+    k = wavevector(shape, spacing, half_x=True)
+    Eh = [scipy.fft.rfftn(np.asarray(E[a], np.float64), workers=workers) for a in range(3)]
+    Bh = [scipy.fft.rfftn(np.asarray(B[a], np.float64), workers=workers) for a in range(3)]
+    Jh = [scipy.fft.rfftn(np.asarray(J[a], np.float64), workers=workers) for a in range(3)]
+    En, Bn = update_with_current(Eh, Bh, Jh, k, dt, project_b)
+    E = np.stack([scipy.fft.irfftn(x, s=shape, workers=workers) for x in En])
+    B = np.stack([scipy.fft.irfftn(x, s=shape, workers=workers) for x in Bn])
+    return E, B
 
 
 def step_direct(E, B, spacing, dt, project_b=False):

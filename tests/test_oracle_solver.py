@@ -204,3 +204,98 @@ def test_nyquist_modes_with_signed_reading_would_break_reality():
     En, _ = psatd.update(Eh, Bh, k, 0.7)
     im = max(np.abs(dft.idftn(x).imag).max() for x in En)
     assert im > 1e-3
+
+
+# ---------------------------------------------------------------- currents
+def _cross_matrix(k):
+    """K with K v = k x v."""
+    return np.array([[0.0, -k[2], k[1]], [k[2], 0.0, -k[0]], [-k[1], k[0], 0.0]])
+
+
+def _maxwell_mode_exact(k, E, B, J, dt):
+    """Exact solution of d/dt E = i c k x B - 4 pi J, d/dt B = -i c k x E
+    (CGS, c = 1; Maxwell's curl equations for one Fourier mode with grad ->
+    +ik) over dt with J constant: the matrix exponential of the system
+    augmented by a constant state."""
+    import scipy.linalg
+    K = _cross_matrix(k)
+    A = np.zeros((7, 7), complex)
+    A[0:3, 3:6] = 1j * K
+    A[3:6, 0:3] = -1j * K
+    A[0:3, 6] = -4.0 * np.pi * J
+    y = scipy.linalg.expm(A * dt) @ np.concatenate([E, B, [1.0]])
+    return y[0:3], y[3:6]
+
+
+@pytest.mark.parametrize("dt", [0.013, 0.7, 23.0, -1.9])
+def test_current_step_is_the_exact_solution_of_maxwells_equations_per_mode(dt):
+    """Eqs. (1)-(2) against the matrix exponential of the curl equations with
+    a constant current, for random modes (k = 0 included), complex E (with a
+    longitudinal part) and j, and B with k . B = 0 (Eq. (2), like Eq. (4),
+    holds for B without magnetic charge: a longitudinal B is constant in
+    Maxwell's equations but would be multiplied by C)."""
+    rng = np.random.default_rng(11)
+    for trial in range(20):
+        k = rng.standard_normal(3) * (0.0 if trial == 0 else rng.uniform(0.1, 4.0))
+        E, B, J = (rng.standard_normal(3) + 1j * rng.standard_normal(3) for _ in range(3))
+        if trial:
+            B = B - k * (k @ B) / (k @ k)
+        Ee, Be = _maxwell_mode_exact(k, E, B, J, dt)
+        kk = tuple(np.array(x) for x in k)
+        En, Bn = psatd.update_with_current(list(E), list(B), list(J), kk, dt)
+        got = np.concatenate([np.array(En, complex).ravel(), np.array(Bn, complex).ravel()])
+        ref = np.concatenate([Ee, Be])
+        assert np.abs(got - ref).max() <= 1e-11 * max(1.0, np.abs(ref).max()), (trial, dt)
+
+
+def test_current_step_semigroup_for_a_constant_current():
+    """With the current held constant, two steps of dt equal one of 2 dt
+    (Eqs. (1)-(2) are the exact solution over any interval) for B without
+    magnetic charge."""
+    shape, sp = (8, 10, 12), (0.3, 0.25, 0.2)
+    rng = np.random.default_rng(5)
+    E, B, J = (rng.standard_normal((3,) + shape) for _ in range(3))
+    _, B = psatd.step_fft(E, B, sp, 0.0, project_b_first=True)
+    E1, B1 = psatd.step_fft_current(E, B, J, sp, 0.37)
+    E2, B2 = psatd.step_fft_current(E1, B1, J, sp, 0.37)
+    E3, B3 = psatd.step_fft_current(E, B, J, sp, 0.74)
+    ref = np.concatenate([E3, B3])
+    assert np.abs(np.concatenate([E2, B2]) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_current_step_without_current_on_transverse_fields_is_the_vacuum_step():
+    """j = 0 and div E = 0: Eqs. (1)-(2) reduce to Eqs. (3)-(4)."""
+    shape, sp = (8, 10, 12), (0.3, 0.25, 0.2)
+    E, B = planewaves.random_fields(3, shape)
+    E, B = psatd.step_fft(E, B, sp, 0.0, project_b_first=True)
+    Ec, Bc = psatd.step_fft_current(E, B, np.zeros_like(E), sp, 0.9)
+    Ev, Bv = psatd.step_fft(E, B, sp, 0.9)
+    assert np.abs(np.concatenate([Ec - Ev, Bc - Bv])).max() <= 1e-13
+
+
+def test_uniform_current_ramps_the_uniform_field():
+    """A uniform current from zero fields: E = -4 pi dt j everywhere, B = 0
+    (the k = 0 limits S / (kappa c) -> dt, (1 - C) / (kappa c) -> 0)."""
+    shape, sp = (6, 8, 10), (0.3, 0.25, 0.2)
+    j0 = np.array([0.3, -1.2, 0.7])
+    J = np.broadcast_to(j0[:, None, None, None], (3,) + shape).copy()
+    Z = np.zeros((3,) + shape)
+    E, B = psatd.step_fft_current(Z, Z, J, sp, 0.45)
+    assert np.abs(E - (-4.0 * np.pi * 0.45) * J).max() <= 1e-13
+    assert np.abs(B).max() <= 1e-13
+
+
+def test_current_step_keeps_gauss_law_with_charge_continuity():
+    """k . (E' - E) = -4 pi dt k . j for every mode: the charge the current
+    moves, div E changing by -4 pi dt div j."""
+    import scipy.fft
+    shape, sp = (8, 10, 12), (0.3, 0.25, 0.2)
+    rng = np.random.default_rng(9)
+    E, B, J = (rng.standard_normal((3,) + shape) for _ in range(3))
+    E1, _ = psatd.step_fft_current(E, B, J, sp, 1.3)
+    k = psatd.wavevector(shape, sp, half_x=True)
+    dEh = [scipy.fft.rfftn(E1[a] - E[a]) for a in range(3)]
+    Jh = [scipy.fft.rfftn(J[a]) for a in range(3)]
+    lhs = sum(k[a] * dEh[a] for a in range(3))
+    rhs = -4.0 * np.pi * 1.3 * sum(k[a] * Jh[a] for a in range(3))
+    assert np.abs(lhs - rhs).max() <= 1e-10 * np.abs(rhs).max()

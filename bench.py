@@ -41,8 +41,8 @@ PASS_BYTES_PER_CELL = {"f32": 48, "f64": 96}   # read + write of six components
 
 def pass_kernels(plan, nz):
     """Kernel (rocprofv3 short name) behind each pass of a step under a kernel
-    plan (row_block, fast, zvariant) with nz-point z columns."""
-    _, fast, zv = plan
+    plan (row_block, fast, zvariant, ...) with nz-point z columns."""
+    _, fast, zv = plan[:3]
     if not fast:
         z, col = "k_z", "k_col"
     else:

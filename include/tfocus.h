@@ -79,8 +79,8 @@ typedef enum {
 
 /* Periodic grid; the layer period along x is D = nx * dx. */
 typedef struct {
-    int32_t nx, ny, nz;   /* nx even; each length a product of 2s and 3s,
-                             8 <= n <= 1024 (tf_supported_length)               */
+    int32_t nx, ny, nz;   /* nx even; each length one tf_supported_length
+                             accepts                                            */
     int32_t replicate_yz; /* 0: the grid holds the pulse transversely.  1: y and
                              z are periods of the mapping too (transverse
                              duplication, Sec. II.C closing remarks): every
@@ -150,7 +150,10 @@ const char* tf_version(void);
 /* Message of the calling thread's last failure ("" if none). */
 const char* tf_last_error(void);
 
-/* 1 if n is a supported axis length (product of 2s and 3s in [8, 1024]). */
+/* 1 if n is a supported axis length: 2^a (8 .. 1024), 3 2^a (24 .. 768),
+ * 5 2^a (40 .. 640) or 7 2^a (56 .. 896).  Lengths with a factor 5 or 7
+ * (the paper's 112 and 896 node axes, Sec. III.A) take radix-5 and radix-7
+ * stages and run the generic y and z kernels. */
 int32_t tf_supported_length(int32_t n);
 
 /* Host only.  Opening angle (Sec. II.B), amplitude (Eq. (9); Gaussian
@@ -212,6 +215,26 @@ tf_status tf_set_cutout(tf_solver* s, double R_min, double R_max);
  * after tf_set_pulse, the remainder and all steps while tf_profile is on
  * are launched directly.  Both give the same bits. */
 tf_status tf_advance(tf_solver* s, int64_t nsteps, double dt);
+
+/* One step of dt with a current density j held over the step (Sec. II.A,
+ * Eqs. (1)-(2), CGS units, c = 1):
+ *   E' = C E + i S k_hat x B - (4 pi S / |k|) j + (1 - C) k_hat (k_hat . E)
+ *        + 4 pi k_hat (k_hat . j) (S / |k| - dt)
+ *   B' = C B - i S k_hat x E + 4 pi i ((1 - C) / |k|) k_hat x j
+ * per mode, between the forward and inverse 3-D FFTs, with the conventions
+ * of tf_advance.  At |k| = 0 the factors S / |k| and (1 - C) / |k| take
+ * their limits dt and 0, so a uniform current gives E' = E - 4 pi dt j.
+ * The longitudinal part of E is kept (it changes by -4 pi dt k_hat . j);
+ * after tf_set_pulse the longitudinal part of B is removed first, as in
+ * tf_advance.  j: 3 nx ny nz elements of the solver's precision, layout
+ * [component][z][y][x] (jx, jy, jz), x fastest, on the host (j_on_device =
+ * 0; the call then waits for the copy) or on the solver's device (1),
+ * borrowed for the call.  The first call allocates a six-component current
+ * array and a second half spectrum (12 nx ny nz elements), kept until
+ * tf_destroy.  t += dt.  Asynchronous on the solver's stream for device j.
+ * TF_EUNSUPPORTED where nine z columns do not fit the LDS (float64 with
+ * nz = 1024); TF_ENOMEM above TFOCUS_MAX_DEVICE_BYTES. */
+tf_status tf_advance_current(tf_solver* s, const void* j, int32_t j_on_device, double dt);
 
 /* Focal window [6][wz][wy][wx] at the current time: u(R) = u~(T(R)) I_S(t)(R),
  * Eqs. (14)-(16), with the third case of Eq. (15) read as "x >= 0 and
@@ -310,12 +333,13 @@ tf_status tf_set_plan_file(const char* path);
 /* Host only.  The kernel plan tf_create and tf_batch_create use for a grid:
  * the y row blocking of the spectrum, whether the fast float32 kernels may
  * run (0 selects the generic kernels; also 0 when the fast z kernel's 32-bit
- * strip offsets would not reach a row of the spectrum), and the fast z
- * kernel's strip shape.  From the plan file, then the environment overrides
- * TFOCUS_ROW_BLOCK, TFOCUS_GENERIC_KERNELS and TFOCUS_ZVARIANT.  Any output
- * pointer may be NULL. */
+ * strip offsets would not reach a row of the spectrum), the fast z kernel's
+ * strip shape, and the columns per strip of the fast y kernel (64, i.e.
+ * 512-byte strips, or 32).  From the plan file, then the environment
+ * overrides TFOCUS_ROW_BLOCK, TFOCUS_GENERIC_KERNELS, TFOCUS_ZVARIANT and
+ * TFOCUS_YSTRIP.  Any output pointer may be NULL. */
 tf_status tf_kernel_plan(const tf_grid* grid, int32_t precision, int32_t* row_block, int32_t* fast,
-                         int32_t* zvariant);
+                         int32_t* zvariant, int32_t* ystrip);
 
 /* For each cube size N in sizes[0..n): time a few steps of every kernel
  * plan (y row blocking 8 or none; generic kernels or the fast float32

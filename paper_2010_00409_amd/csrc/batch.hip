@@ -51,7 +51,32 @@ std::string device_arch() {
     return c == std::string::npos ? a : a.substr(0, c);
 }
 
-// Plan file: '#' comments; entries "arch prec nx ny nz row_block fast zvariant ms".
+// Plan file: '#' comments; entries
+// "arch prec nx ny nz row_block fast zvariant ystrip ms" (lines without the
+// ystrip field keep 64-column y strips).  False for comments and bad lines.
+bool parse_plan_line(const std::string& line, PlanKey& k, KernelPlan& p, double& ms) {
+    if (line.empty() || line[0] == '#') return false;
+    std::istringstream is(line);
+    std::vector<std::string> t;
+    for (std::string w; is >> w;) t.push_back(w);
+    if (t.size() != 9 && t.size() != 10) return false;
+    try {
+        k.arch = t[0];
+        k.prec = t[1] == "f64" ? TF_F64 : TF_F32;
+        k.nx = std::stoi(t[2]);
+        k.ny = std::stoi(t[3]);
+        k.nz = std::stoi(t[4]);
+        p.row_block = std::stoi(t[5]);
+        p.fast = std::stoi(t[6]) != 0;
+        p.zvariant = std::stoi(t[7]);
+        p.ystrip = t.size() == 10 ? std::stoi(t[8]) : 64;
+        ms = std::stod(t.back());
+    } catch (...) {
+        return false;
+    }
+    return p.row_block > 0 && (p.ystrip == 64 || p.ystrip == 32);
+}
+
 void load_plans_locked() {
     if (g_plan_loaded) return;
     g_plan_loaded = true;
@@ -60,17 +85,10 @@ void load_plans_locked() {
     std::ifstream f(g_plan_path);
     std::string line;
     while (std::getline(f, line)) {
-        if (line.empty() || line[0] == '#') continue;
-        std::istringstream is(line);
         PlanKey k;
-        std::string prec;
         KernelPlan p;
-        int fast = 1;
         double ms = 0.0;
-        if (!(is >> k.arch >> prec >> k.nx >> k.ny >> k.nz >> p.row_block >> fast >> p.zvariant >> ms)) continue;
-        k.prec = prec == "f64" ? TF_F64 : TF_F32;
-        p.fast = fast != 0;
-        g_plans[k] = p;
+        if (parse_plan_line(line, k, p, ms)) g_plans[k] = p;
     }
 }
 
@@ -81,6 +99,10 @@ void env_overrides(const tf_grid& g, KernelPlan& p) {
     }
     if (const char* v = std::getenv("TFOCUS_GENERIC_KERNELS")) p.fast = !(v[0] == '1');
     if (const char* v = std::getenv("TFOCUS_ZVARIANT")) p.zvariant = std::atoi(v);
+    if (const char* v = std::getenv("TFOCUS_YSTRIP")) {
+        const int w = std::atoi(v);
+        if (w == 64 || w == 32) p.ystrip = w;
+    }
 }
 
 }  // namespace
@@ -476,7 +498,7 @@ tf_status tf_batch_destroy(tf_batch* b) {
 }
 
 tf_status tf_kernel_plan(const tf_grid* grid, int32_t precision, int32_t* row_block, int32_t* fast,
-                         int32_t* zvariant) {
+                         int32_t* zvariant, int32_t* ystrip) {
     if (precision != TF_F32 && precision != TF_F64) return fail(TF_EINVAL, "precision must be TF_F32 or TF_F64");
     tf_status st = validate_grid(grid);
     if (st != TF_OK) return st;
@@ -484,6 +506,7 @@ tf_status tf_kernel_plan(const tf_grid* grid, int32_t precision, int32_t* row_bl
     if (row_block) *row_block = p.row_block;
     if (fast) *fast = p.fast ? 1 : 0;
     if (zvariant) *zvariant = p.zvariant;
+    if (ystrip) *ystrip = p.ystrip;
     return TF_OK;
 }
 
@@ -531,11 +554,13 @@ tf_status tf_tune(const int32_t* sizes, int32_t n, int32_t precision, const char
             if (!fast_offsets_fit(g, rb, precision)) continue;
             // variants 7 and 8 (one wave per mode) exist for 512-point z
             // columns; elsewhere they run variant 6
-            for (int zv = 0; zv < (N == 512 ? 9 : 7); ++zv) {
-                p.fast = true;
-                p.zvariant = zv;
-                cands.push_back(p);
-            }
+            for (int ys : {64, 32})
+                for (int zv = 0; zv < (N == 512 ? 9 : 7); ++zv) {
+                    p.fast = true;
+                    p.zvariant = zv;
+                    p.ystrip = ys;
+                    cands.push_back(p);
+                }
         }
         TF_HIP(hipEventCreate(&tb.e0));
         TF_HIP(hipEventCreate(&tb.e1));
@@ -581,29 +606,23 @@ tf_status tf_tune(const int32_t* sizes, int32_t n, int32_t precision, const char
         std::ifstream f(plan_path);
         std::string line;
         while (std::getline(f, line)) {
-            if (line.empty() || line[0] == '#') continue;
-            std::istringstream is(line);
             PlanKey k;
-            std::string prec;
             KernelPlan p;
-            int fast = 1;
             double ms = 0.0;
-            if (!(is >> k.arch >> prec >> k.nx >> k.ny >> k.nz >> p.row_block >> fast >> p.zvariant >> ms)) continue;
-            k.prec = prec == "f64" ? TF_F64 : TF_F32;
-            p.fast = fast != 0;
-            all[k] = {p, ms};
+            if (parse_plan_line(line, k, p, ms)) all[k] = {p, ms};
         }
     }
     for (auto& kv : found) all[kv.first] = kv.second;
     std::ofstream f(plan_path);
     if (!f) return fail(TF_EINVAL, std::string("cannot write ") + plan_path);
-    f << "# tfocus kernel plans: arch precision nx ny nz row_block fast zvariant ms_per_step\n";
+    f << "# tfocus kernel plans: arch precision nx ny nz row_block fast zvariant ystrip ms_per_step\n";
     for (auto& kv : all) {
         const PlanKey& k = kv.first;
         const KernelPlan& p = kv.second.first;
         char buf[256];
-        std::snprintf(buf, sizeof(buf), "%s %s %d %d %d %d %d %d %.4f\n", k.arch.c_str(), k.prec == TF_F64 ? "f64" : "f32",
-                      k.nx, k.ny, k.nz, p.row_block, p.fast ? 1 : 0, p.zvariant, kv.second.second);
+        std::snprintf(buf, sizeof(buf), "%s %s %d %d %d %d %d %d %d %.4f\n", k.arch.c_str(),
+                      k.prec == TF_F64 ? "f64" : "f32", k.nx, k.ny, k.nz, p.row_block, p.fast ? 1 : 0, p.zvariant,
+                      p.ystrip, kv.second.second);
         f << buf;
     }
     {

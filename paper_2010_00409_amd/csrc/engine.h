@@ -34,11 +34,7 @@ inline tf_status fail(tf_status st, const std::string& msg) {
     } while (0)
 
 inline bool length_ok(int n) {
-    if (n < 8 || n > 1024) return false;
-    int m = n;
-    while (m % 2 == 0) m /= 2;
-    while (m % 3 == 0) m /= 3;
-    return m == 1 && tf::fft_length_supported(n);
+    return n >= 8 && n <= 1024 && tf::fft_length_supported(n);
 }
 
 inline bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -303,7 +299,7 @@ inline tf_status validate_grid(const tf_grid* grid) {
     for (int n : {grid->nx, grid->ny, grid->nz})
         if (!length_ok(n))
             return fail(TF_EUNSUPPORTED, "axis length " + std::to_string(n) +
-                                             " unsupported (products of 2 and 3, 8..1024)");
+                                             " unsupported (see tf_supported_length)");
     return TF_OK;
 }
 
@@ -314,6 +310,8 @@ struct KernelPlan {
     int row_block = 8;
     bool fast = true;
     int zvariant = 0;
+    int ystrip = 64;       // columns per strip of the fast y kernel (64 or 32)
+    int yarg() const { return fast ? ystrip : 0; }
 };
 KernelPlan plan_for(const tf_grid& g, int precision);
 
@@ -330,12 +328,12 @@ hipError_t step_passes(void* state, void* spec, void* const* tw, const tf_grid& 
                        const KernelPlan& kp, double dt, bool project_b, Batch bt, hipStream_t st) {
     hipError_t e = launch_x_forward<T>(static_cast<const T*>(state), spec, tw[0], g.nx, g.ny, g.nz, rm, bt, st);
     if (e != hipSuccess) return e;
-    e = launch_y_pass<T>(spec, tw[1], g.nx, g.ny, g.nz, -1, rm, kp.fast, bt, st);
+    e = launch_y_pass<T>(spec, tw[1], g.nx, g.ny, g.nz, -1, rm, kp.yarg(), bt, st);
     if (e != hipSuccess) return e;
     StepParams p = step_params(g, dt, project_b, kp.zvariant);
     e = launch_z_pass<T>(spec, tw[2], p, rm, Z_STEP, nullptr, nullptr, nullptr, kp.fast, bt, st);
     if (e != hipSuccess) return e;
-    e = launch_y_pass<T>(spec, tw[1], g.nx, g.ny, g.nz, +1, rm, kp.fast, bt, st);
+    e = launch_y_pass<T>(spec, tw[1], g.nx, g.ny, g.nz, +1, rm, kp.yarg(), bt, st);
     if (e != hipSuccess) return e;
     return launch_x_inverse<T>(spec, static_cast<T*>(state), tw[0], g.nx, g.ny, g.nz, rm, bt, st);
 }

@@ -1,5 +1,6 @@
 // Device building blocks of the spectral step: complex arithmetic, radix
-// 2/3/4/8 butterflies and a Stockham autosort FFT over sequences held in LDS.
+// 2/3/4/5/7/8 butterflies and a Stockham autosort FFT over sequences held in
+// LDS.
 //
 // Transform convention (the forward transform of the spectral solver,
 // Sec. II.A): X[m] = sum_j x[j] w^(m j) with w = exp(DIR 2 pi i / N),
@@ -78,25 +79,79 @@ template <typename T, int DIR> __device__ __forceinline__ void dft8(C2<T>* v) {
     for (int m = 0; m < 4; ++m) { v[2 * m] = b[m]; v[2 * m + 1] = c[m]; }
 }
 
+// cos and sin of 2 pi k / R for odd R = 5, 7 and k = 1 .. (R - 1) / 2
+// (the real and imaginary parts of the R-th roots of unity).
+template <int R> struct OddRoots;
+template <> struct OddRoots<5> {
+    static constexpr double c[2] = {0.30901699437494742410, -0.80901699437494742410};
+    static constexpr double s[2] = {0.95105651629515357212, 0.58778525229247312917};
+};
+template <> struct OddRoots<7> {
+    static constexpr double c[3] = {0.62348980185873353053, -0.22252093395631440429, -0.90096886790241912624};
+    static constexpr double s[3] = {0.78183148246802980871, 0.97492791218182360702, 0.43388373911755812048};
+};
+
+// Length-R DFT for odd prime R from symmetric pairs: with a_j = x_j + x_{R-j}
+// and b_j = x_j - x_{R-j}, X_m = x_0 + sum_j a_j cos(2 pi j m / R)
+// + DIR i sum_j b_j sin(2 pi j m / R), and X_{R-m} the same with the sine
+// sum negated (m = 1 .. (R - 1) / 2).
+template <typename T, int R, int DIR> __device__ __forceinline__ void dft_odd(C2<T>* v) {
+    constexpr int H = (R - 1) / 2;
+    C2<T> a[H], b[H];
+#pragma unroll
+    for (int j = 1; j <= H; ++j) { a[j - 1] = cadd(v[j], v[R - j]); b[j - 1] = csub(v[j], v[R - j]); }
+    const C2<T> x0 = v[0];
+    C2<T> sum = x0;
+#pragma unroll
+    for (int j = 0; j < H; ++j) sum = cadd(sum, a[j]);
+    v[0] = sum;
+#pragma unroll
+    for (int m = 1; m <= H; ++m) {
+        C2<T> re = x0, im{T(0), T(0)};
+#pragma unroll
+        for (int j = 1; j <= H; ++j) {
+            const int k = (j * m) % R;                       // angle index of j m, folded to 1 .. H
+            const int kk = k <= H ? k : R - k;
+            const T cj = T(OddRoots<R>::c[kk - 1]);
+            const T sj = T(k <= H ? OddRoots<R>::s[kk - 1] : -OddRoots<R>::s[kk - 1]);
+            re.x += cj * a[j - 1].x; re.y += cj * a[j - 1].y;
+            im.x += sj * b[j - 1].x; im.y += sj * b[j - 1].y;
+        }
+        const C2<T> t = cmul_i<DIR>(im);
+        v[m] = cadd(re, t);
+        v[R - m] = csub(re, t);
+    }
+}
+
 template <typename T, int R, int DIR> __device__ __forceinline__ void dftR(C2<T>* v) {
+    static_assert(R == 2 || R == 3 || R == 4 || R == 5 || R == 7 || R == 8, "radix 2, 3, 4, 5, 7 or 8");
     if constexpr (R == 2) dft2<T, DIR>(v);
     else if constexpr (R == 3) dft3<T, DIR>(v);
     else if constexpr (R == 4) dft4<T, DIR>(v);
+    else if constexpr (R == 5 || R == 7) dft_odd<T, R, DIR>(v);
     else dft8<T, DIR>(v);
 }
 
-// Radix schedule of a length N = 2^a 3^b: radix-8 stages, then one radix-4
-// or radix-2 stage for the rest of the power of two, then radix-3 stages.
+// Radix schedule of a length N = 2^a 3^b 5^c 7^d: radix-8 stages, then one
+// radix-4 or radix-2 stage for the rest of the power of two, then radix-3,
+// radix-5 and radix-7 stages.
 constexpr int log2_part(int n) { int a = 0; while (n % 2 == 0) { n /= 2; ++a; } return a; }
 constexpr int log3_part(int n) { int b = 0; while (n % 3 == 0) { n /= 3; ++b; } return b; }
+constexpr int logp_part(int n, int p) { int b = 0; while (n % p == 0) { n /= p; ++b; } return b; }
+constexpr int ipow(int p, int e) { int r = 1; while (e-- > 0) r *= p; return r; }
 template <int N> struct Plan {
     static constexpr int a = log2_part(N);
     static constexpr int b = log3_part(N);
+    static constexpr int c5 = logp_part(N, 5);
+    static constexpr int c7 = logp_part(N, 7);
     static constexpr int n8 = a / 3;
     static constexpr int rem = a % 3;
-    static constexpr int nst = n8 + (rem ? 1 : 0) + b;
-    static constexpr int radix(int s) { return s < n8 ? 8 : ((rem && s == n8) ? (1 << rem) : 3); }
-    static_assert(N == (1 << a) * (b == 0 ? 1 : (b == 1 ? 3 : (b == 2 ? 9 : 27))), "N must be 2^a 3^b");
+    static constexpr int n2 = n8 + (rem ? 1 : 0);
+    static constexpr int nst = n2 + b + c5 + c7;
+    static constexpr int radix(int s) {
+        return s < n8 ? 8 : (s < n2 ? (1 << rem) : (s < n2 + b ? 3 : (s < n2 + b + c5 ? 5 : 7)));
+    }
+    static_assert(N == (1 << a) * ipow(3, b) * ipow(5, c5) * ipow(7, c7), "N must be 2^a 3^b 5^c 7^d");
 };
 
 // LDS placement of element n of sequence s: one pad slot every 32 elements
@@ -170,18 +225,22 @@ __device__ __forceinline__ void fft_lds(C2<T>* buf, const C2<T>* tw, int tid) {
 template <int N, int E> struct LGPlan {
     static constexpr int a = log2_part(N);
     static constexpr int b = log3_part(N);
+    static constexpr int c5 = logp_part(N, 5);
+    static constexpr int c7 = logp_part(N, 7);
     static constexpr int ea = log2_part(E);
-    static constexpr int eb = log3_part(E);
-    // radix-8 stages if 8 | E, then one 4 or 2, then radix-3 stages
+    // radix-8 stages if 8 | E, then 4s (if 4 | E) and 2s, then radix-3, 5, 7
     static constexpr int r8 = (ea >= 3) ? a / 3 : 0;
     static constexpr int rest = a - 3 * r8;              // remaining power of two
     static constexpr int n4 = (ea >= 2) ? rest / 2 : 0;
     static constexpr int n2 = rest - 2 * n4;
-    static constexpr int nst = r8 + n4 + n2 + b;
+    static constexpr int p2 = r8 + n4 + n2;
+    static constexpr int nst = p2 + b + c5 + c7;
     static constexpr int radix(int s) {
-        return s < r8 ? 8 : (s < r8 + n4 ? 4 : (s < r8 + n4 + n2 ? 2 : 3));
+        return s < r8 ? 8 : (s < r8 + n4 ? 4 : (s < p2 ? 2 : (s < p2 + b ? 3 : (s < p2 + b + c5 ? 5 : 7))));
     }
-    static_assert(b == 0 || eb >= 1, "radix-3 stages need 3 | E");
+    static_assert(b == 0 || E % 3 == 0, "radix-3 stages need 3 | E");
+    static_assert(c5 == 0 || E % 5 == 0, "radix-5 stages need 5 | E");
+    static_assert(c7 == 0 || E % 7 == 0, "radix-7 stages need 7 | E");
     static_assert(N % E == 0 && (N / E) <= 1024, "bad lane-group shape");
 };
 

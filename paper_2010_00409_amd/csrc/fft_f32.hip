@@ -4,10 +4,12 @@
 namespace tf {
 template hipError_t launch_x_forward<float>(const float*, void*, const void*, int, int, int, RowMap, Batch, hipStream_t);
 template hipError_t launch_x_inverse<float>(const void*, float*, const void*, int, int, int, RowMap, Batch, hipStream_t);
-template hipError_t launch_y_pass<float>(void*, const void*, int, int, int, int, RowMap, bool, Batch, hipStream_t);
+template hipError_t launch_y_pass<float>(void*, const void*, int, int, int, int, RowMap, int, Batch, hipStream_t);
 template hipError_t launch_z_pass<float>(void*, const void*, const StepParams&, RowMap, int, double*, void*, int*, bool,
                                        Batch, hipStream_t);
 template int z_diag_blocks<float>(int, int, int);
+template hipError_t launch_z_current<float>(void*, const void*, const void*, const StepParams&, RowMap, hipStream_t);
+template bool z_current_supported<float>(int);
 }  // namespace tf
 
 namespace tf {

@@ -55,9 +55,10 @@ template <typename T> hipError_t launch_x_forward(const T* real, void* spec, con
 template <typename T> hipError_t launch_x_inverse(const void* spec, T* real, const void* tw,
                                                   int nx, int ny, int nz, RowMap rm, Batch bt, hipStream_t st);
 // In-place y transform of the spectral array, dir = -1 forward, +1 inverse.
-// fast = false forces the generic kernels.
+// ystrip: columns per strip of the fast float32 kernel (64 or 32; 64 falls
+// back to 32 on rows of 32 (mod 64) slots); 0 forces the generic kernels.
 template <typename T> hipError_t launch_y_pass(void* spec, const void* tw, int nx, int ny, int nz,
-                                               int dir, RowMap rm, bool fast, Batch bt, hipStream_t st);
+                                               int dir, RowMap rm, int ystrip, Batch bt, hipStream_t st);
 // z pass: Z_STEP = forward z FFT, Eqs. (3)-(4) update, inverse z FFT, in place;
 // Z_DIAG = forward z FFT and per-block maxima |k.E|, |k.B|, |E|, |B| into
 // partials (4 doubles per block; the packed kx = 0 slot goes through dc, a
@@ -67,6 +68,13 @@ template <typename T> hipError_t launch_z_pass(void* spec, const void* tw, const
                                                RowMap rm, int mode, double* partials, void* dc,
                                                int* nblocks, bool fast, Batch bt, hipStream_t st);
 template <typename T> int z_diag_blocks(int nx, int ny, int nz);
+// z pass of a step with a current (Eqs. (1)-(2)): jspec holds the x- and
+// y-transformed current in components 0..2 of the same layout as spec.
+// Generic kernel, one mode slot per block, for every nz whose nine columns
+// fit the LDS (z_current_supported).
+template <typename T> hipError_t launch_z_current(void* spec, const void* jspec, const void* tw,
+                                                  const StepParams& p, RowMap rm, hipStream_t st);
+template <typename T> bool z_current_supported(int nz);
 
 // Twiddle tables are per axis length: tw[e] = exp(-2 pi i e / n).
 bool fft_length_supported(int n);

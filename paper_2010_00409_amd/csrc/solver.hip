@@ -41,9 +41,14 @@ struct tf_solver {
     void* dcbuf = nullptr;         // diagnostics: packed kx = 0 slot after the forward z FFT
     tf::RowMap rm{};
     bool fast = true;              // use the specialised float32 column kernels
+    int ystrip = 64;               // columns per strip of the fast y kernel
     int zvariant = 0;
     void* scratch_out = nullptr;
     size_t scratch_bytes = 0;
+    // current steps (tf_advance_current): the current in components 0..2 of
+    // a six-component real array (3..5 stay zero) and its half spectrum
+    void* jstate = nullptr;
+    void* jspec = nullptr;
     double t = 0.0;
     bool project_b_next = false;
     bool have_cutout = false;
@@ -90,7 +95,41 @@ hipError_t forward_xy(tf_solver* s, int kind_x, int kind_y) {
     });
     if (e != hipSuccess) return e;
     return timed(s, kind_y, [&] {
-        return tf::launch_y_pass<T>(s->spec, s->tw[1], g.nx, g.ny, g.nz, -1, s->rm, s->fast, tf::Batch{}, s->stream);
+        return tf::launch_y_pass<T>(s->spec, s->tw[1], g.nx, g.ny, g.nz, -1, s->rm, s->fast ? s->ystrip : 0,
+                                    tf::Batch{}, s->stream);
+    });
+}
+
+// One step of Eqs. (1)-(2) with the current in s->jstate: the current and
+// the fields are x- and y-transformed, the z pass applies the update, and
+// the fields go back as in a vacuum step.
+template <typename T>
+hipError_t current_step(tf_solver* s, double dt, bool project_b) {
+    const tf_grid& g = s->grid;
+    const int ys = s->fast ? s->ystrip : 0;
+    hipError_t e = timed(s, TF_PASS_OTHER, [&] {
+        return tf::launch_x_forward<T>(static_cast<const T*>(s->jstate), s->jspec, s->tw[0], g.nx, g.ny, g.nz, s->rm,
+                                       tf::Batch{}, s->stream);
+    });
+    if (e != hipSuccess) return e;
+    e = timed(s, TF_PASS_OTHER, [&] {
+        return tf::launch_y_pass<T>(s->jspec, s->tw[1], g.nx, g.ny, g.nz, -1, s->rm, ys, tf::Batch{}, s->stream);
+    });
+    if (e != hipSuccess) return e;
+    e = forward_xy<T>(s, TF_PASS_X_FORWARD, TF_PASS_Y_FORWARD);
+    if (e != hipSuccess) return e;
+    tf::StepParams p = step_params(s->grid, dt, project_b, s->zvariant);
+    e = timed(s, TF_PASS_Z_STEP, [&] {
+        return tf::launch_z_current<T>(s->spec, s->jspec, s->tw[2], p, s->rm, s->stream);
+    });
+    if (e != hipSuccess) return e;
+    e = timed(s, TF_PASS_Y_INVERSE, [&] {
+        return tf::launch_y_pass<T>(s->spec, s->tw[1], g.nx, g.ny, g.nz, +1, s->rm, ys, tf::Batch{}, s->stream);
+    });
+    if (e != hipSuccess) return e;
+    return timed(s, TF_PASS_X_INVERSE, [&] {
+        return tf::launch_x_inverse<T>(s->spec, static_cast<T*>(s->state), s->tw[0], g.nx, g.ny, g.nz, s->rm,
+                                       tf::Batch{}, s->stream);
     });
 }
 
@@ -106,7 +145,8 @@ hipError_t one_step(tf_solver* s, double dt, bool project_b) {
     });
     if (e != hipSuccess) return e;
     e = timed(s, TF_PASS_Y_INVERSE, [&] {
-        return tf::launch_y_pass<T>(s->spec, s->tw[1], g.nx, g.ny, g.nz, +1, s->rm, s->fast, tf::Batch{}, s->stream);
+        return tf::launch_y_pass<T>(s->spec, s->tw[1], g.nx, g.ny, g.nz, +1, s->rm, s->fast ? s->ystrip : 0,
+                                    tf::Batch{}, s->stream);
     });
     if (e != hipSuccess) return e;
     return timed(s, TF_PASS_X_INVERSE, [&] {
@@ -159,7 +199,7 @@ void free_all(tf_solver* s) {
     for (hipEvent_t ev : s->evpool) (void)hipEventDestroy(ev);
     s->evpool.clear();
     void* ptrs[] = {s->state, s->spec, s->tw[0], s->tw[1], s->tw[2], s->partials, s->results,
-                    s->pulse_tab, s->dcbuf, s->scratch_out};
+                    s->pulse_tab, s->dcbuf, s->scratch_out, s->jstate, s->jspec};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -332,6 +372,7 @@ tf_status tf_create(const tf_grid* grid, int32_t precision, void* hip_stream, tf
     s->rm.G = kp.row_block;
     s->fast = kp.fast;
     s->zvariant = kp.zvariant;
+    s->ystrip = kp.ystrip;
     if (need > device_cap()) {
         delete s;
         return fail(TF_ENOMEM, "solver needs " + std::to_string(need) + " device bytes, above TFOCUS_MAX_DEVICE_BYTES");
@@ -487,6 +528,50 @@ tf_status tf_advance(tf_solver* s, int64_t nsteps, double dt) {
         if (st != TF_OK) return st;
     }
     s->t = s->t + (double)nsteps * dt;
+    return TF_OK;
+}
+
+tf_status tf_advance_current(tf_solver* s, const void* j, int32_t j_on_device, double dt) {
+    if (!s || !j) return fail(TF_EINVAL, "solver and j must not be NULL");
+    if (!std::isfinite(dt)) return fail(TF_EINVAL, "dt must be finite");
+    const bool fits = s->prec == TF_F64 ? tf::z_current_supported<double>(s->grid.nz)
+                                        : tf::z_current_supported<float>(s->grid.nz);
+    if (!fits)
+        return fail(TF_EUNSUPPORTED, "current steps need nine z columns of " + std::to_string(s->grid.nz) +
+                                         " elements in LDS (float64: nz <= 768)");
+    const size_t bytes6 = 6 * (size_t)s->cells * s->esize;
+    const size_t spec_b = (size_t)s->grid.nz * s->grid.ny * s->nkx * 6 * 2 * s->esize;
+    if (!s->jstate || !s->jspec) {
+        const size_t have = bytes6 + spec_b + 2 * s->esize * (size_t)(s->grid.nx + s->grid.ny + s->grid.nz);
+        if (have + bytes6 + spec_b > device_cap())
+            return fail(TF_ENOMEM, "current steps need " + std::to_string(bytes6 + spec_b) +
+                                       " more device bytes, above TFOCUS_MAX_DEVICE_BYTES");
+        if (!s->jstate) {
+            hipError_t e = hipMalloc(&s->jstate, bytes6);
+            if (e != hipSuccess) {
+                s->jstate = nullptr;
+                return fail(e == hipErrorOutOfMemory ? TF_ENOMEM : TF_EDEVICE,
+                            std::string("current buffer: ") + hipGetErrorString(e));
+            }
+            TF_HIP(hipMemsetAsync(static_cast<char*>(s->jstate) + bytes6 / 2, 0, bytes6 / 2, s->stream));
+        }
+        if (!s->jspec) {
+            hipError_t e = hipMalloc(&s->jspec, spec_b);
+            if (e != hipSuccess) {
+                s->jspec = nullptr;
+                return fail(e == hipErrorOutOfMemory ? TF_ENOMEM : TF_EDEVICE,
+                            std::string("current spectrum: ") + hipGetErrorString(e));
+            }
+        }
+    }
+    TF_HIP(hipMemcpyAsync(s->jstate, j, bytes6 / 2, j_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          s->stream));
+    if (!j_on_device) TF_HIP(hipStreamSynchronize(s->stream));
+    const bool pb = s->project_b_next;
+    hipError_t e = s->prec == TF_F64 ? current_step<double>(s, dt, pb) : current_step<float>(s, dt, pb);
+    if (e != hipSuccess) return fail(TF_EDEVICE, std::string("current step: ") + hipGetErrorString(e));
+    s->project_b_next = false;
+    s->t = s->t + dt;
     return TF_OK;
 }
 

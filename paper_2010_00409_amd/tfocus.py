@@ -83,6 +83,7 @@ _SIGS = {
     "tf_set_pulse": ([_P, ctypes.POINTER(tf_pulse), ctypes.POINTER(tf_pulse_info)], ctypes.c_int),
     "tf_set_cutout": ([_P, ctypes.c_double, ctypes.c_double], ctypes.c_int),
     "tf_advance": ([_P, ctypes.c_int64, ctypes.c_double], ctypes.c_int),
+    "tf_advance_current": ([_P, _P, ctypes.c_int32, ctypes.c_double], ctypes.c_int),
     "tf_read_focal": ([_P, ctypes.POINTER(tf_window), _P, ctypes.c_int32], ctypes.c_int),
     "tf_diagnostics": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                         ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
@@ -100,7 +101,8 @@ _SIGS = {
     "tf_advance_noalloc": ([ctypes.POINTER(tf_grid), ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_double,
                             ctypes.c_int32, _P], ctypes.c_int),
     "tf_kernel_plan": ([ctypes.POINTER(tf_grid), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
-                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                        ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "tf_profile": ([_P, ctypes.c_int32], ctypes.c_int),
     "tf_profile_read": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "tf_fno_param_count": ([ctypes.c_int32], ctypes.c_int64),
@@ -296,6 +298,13 @@ def tf_advance(h, nsteps, dt):
     _check(load().tf_advance(h, int(nsteps), float(dt)))
 
 
+def tf_advance_current(h, j, dt):
+    """One step of dt with the current density j (3 x nz x ny x nx of the
+    solver's precision, host array or device tensor) held over the step."""
+    ptr, dev, _, _ = _buffer(j)
+    _check(load().tf_advance_current(h, ctypes.c_void_p(ptr), dev, float(dt)))
+
+
 def tf_read_focal(h, window, dst):
     ptr, dev, _, _ = _buffer(dst)
     _check(load().tf_read_focal(h, ctypes.byref(window_struct(window)), ptr, dev))
@@ -350,12 +359,12 @@ def tf_advance_noalloc(grid, precision, state, nsteps, dt, project_b_first=False
 
 
 def tf_kernel_plan(grid, precision="f32"):
-    """(row_block, fast, zvariant) that tf_create would use for the grid."""
-    rb, fast, zv = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    """(row_block, fast, zvariant, ystrip) that tf_create would use for the grid."""
+    rb, fast, zv, ys = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
     _check(load().tf_kernel_plan(ctypes.byref(grid_struct(grid)), prec, ctypes.byref(rb), ctypes.byref(fast),
-                                 ctypes.byref(zv)))
-    return rb.value, bool(fast.value), zv.value
+                                 ctypes.byref(zv), ctypes.byref(ys)))
+    return rb.value, bool(fast.value), zv.value, ys.value
 
 
 def tf_tune(sizes, precision, plan_path):
@@ -482,6 +491,11 @@ class Solver:
 
     def advance(self, nsteps, dt):
         tf_advance(self.h, nsteps, dt)
+
+    def advance_current(self, j, dt):
+        """One step of dt with the current density j held over the step."""
+        self._expect(j, (3,) + tuple(self.shape[1:]))
+        tf_advance_current(self.h, j, dt)
 
     def read_focal(self, window, dst):
         w = window_struct(window)

@@ -31,9 +31,9 @@ def test_library_exports_every_declared_entry_point():
 
 def test_version_and_supported_lengths():
     assert tf.tf_version().startswith("tfocus")
-    for n in (8, 16, 24, 64, 96, 192, 512, 768, 1024):
+    for n in (8, 16, 24, 64, 96, 192, 512, 768, 1024, 40, 80, 640, 56, 112, 896):
         assert tf.tf_supported_length(n)
-    for n in (4, 10, 100, 2048, 80, 1536):
+    for n in (4, 10, 100, 2048, 72, 88, 1536, 1120):
         assert not tf.tf_supported_length(n)
 
 
@@ -143,13 +143,39 @@ def test_fast_z_kernel_needs_its_strip_offsets_to_fit_32_bits(monkeypatch):
     for grid, rb, fast in ((wide, "512", False), (wide, "8", True),
                            (configs.cube_grid(512, 0.1), "512", True)):
         monkeypatch.setenv("TFOCUS_ROW_BLOCK", rb)
-        got_rb, got_fast, _ = tf.tf_kernel_plan(grid, "f32")
+        got_rb, got_fast, _, _ = tf.tf_kernel_plan(grid, "f32")
         assert got_rb == int(rb) and got_fast == fast, (grid["nx"], rb)
     # the arithmetic behind the decision: last strip offset of the wide grid
     rowb = 6 * (768 // 2) * 8
     assert (511 * 512 + 1) * rowb > 2 ** 32 >= (511 * 8 + 1) * rowb
     with pytest.raises(tf.TfError):
         tf.tf_kernel_plan(dict(wide, nx=100), "f32")
+
+
+def test_plan_file_lines_with_and_without_the_y_strip_width(tmp_path, monkeypatch):
+    """Plan lines carry the y strip width before the timing; older lines
+    without it keep 64-column strips; a bad width drops the line; the
+    TFOCUS_YSTRIP override takes 64 or 32.  Host only (the plan lookup runs
+    before any HIP call; without a device the architecture reads 'unknown')."""
+    for v in ("TFOCUS_ROW_BLOCK", "TFOCUS_GENERIC_KERNELS", "TFOCUS_ZVARIANT", "TFOCUS_YSTRIP"):
+        monkeypatch.delenv(v, raising=False)
+    plan = tmp_path / "plans.txt"
+    plan.write_text("# comment\n"
+                    "unknown f32 128 128 128 128 1 6 32 0.1\n"
+                    "unknown f32 192 192 192 8 1 5 0.3\n"
+                    "unknown f32 256 256 256 256 1 4 48 0.7\n")
+    old = os.environ.get("TFOCUS_PLAN_FILE") or tf.DEFAULT_PLANS
+    tf.tf_set_plan_file(str(plan))
+    try:
+        assert tf.tf_kernel_plan(configs.cube_grid(128, 0.1), "f32") == (128, True, 6, 32)
+        assert tf.tf_kernel_plan(configs.cube_grid(192, 0.1), "f32") == (8, True, 5, 64)
+        assert tf.tf_kernel_plan(configs.cube_grid(256, 0.1), "f32") == (8, True, 0, 64)
+        monkeypatch.setenv("TFOCUS_YSTRIP", "32")
+        assert tf.tf_kernel_plan(configs.cube_grid(192, 0.1), "f32")[3] == 32
+        monkeypatch.setenv("TFOCUS_YSTRIP", "48")
+        assert tf.tf_kernel_plan(configs.cube_grid(192, 0.1), "f32")[3] == 64
+    finally:
+        tf.tf_set_plan_file(old)
 
 
 def test_phase_bumps_are_validated_before_any_hip_call():

@@ -312,6 +312,48 @@ def test_wave_z_kernel_projection_and_huge_phases(zvariant, monkeypatch):
     assert rel(out2.astype(np.float64), np.concatenate([Eo, Bo])) <= F32_TOL
 
 
+@pytest.mark.parametrize("shape", [(64, 64, 64), (128, 128, 128), (192, 192, 192), (256, 256, 256),
+                                   (512, 64, 64), (96, 512, 32)])
+def test_y_strip_width_32_keeps_parity(shape, monkeypatch):
+    """The fast y kernel on 256-byte strips (32 columns), which the tuner may
+    pick instead of 512-byte ones: forward and inverse y passes around every
+    z kernel shape the plans use, two steps against the oracle, including
+    512-point y columns."""
+    monkeypatch.setenv("TFOCUS_YSTRIP", "32")
+    g, st = transverse_state(70 + shape[0] + shape[1], shape, 0.3)
+    rb, fast, _, ys = tf.tf_kernel_plan(g, "f32")
+    assert fast and ys == 32
+    st = st.astype(np.float32).astype(np.float64)
+    out, _ = run_gpu(g, "f32", st, 2, 0.41)
+    Eo, Bo = psatd.step_fft(st[:3], st[3:], spacing(g), 0.41, nsteps=2)
+    assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= 2 * F32_TOL
+
+
+@pytest.mark.parametrize("shape", [(40, 56, 80), (112, 80, 56), (56, 40, 112)])
+def test_radix_5_and_7_lengths_f64_match_the_direct_dft_oracle(shape):
+    """Axis lengths with factors 5 and 7 (radix-5 and radix-7 stages in the x
+    lane groups and in the generic y and z kernels) against the direct-DFT
+    step (oracle O1, no FFT library)."""
+    g, st = transverse_state(90 + shape[0], shape, 0.21)
+    out, _ = run_gpu(g, "f64", st, 1, 0.53)
+    Eo, Bo = psatd.step_direct(st[:3], st[3:], spacing(g), 0.53)
+    assert rel(out, np.concatenate([Eo, Bo])) <= F64_TOL
+
+
+@pytest.mark.parametrize("shape, prec", [((896, 8, 16), "f64"), ((8, 16, 896), "f64"), ((16, 896, 8), "f32"),
+                                         ((160, 224, 320), "f32"), ((448, 40, 640), "f32")])
+def test_radix_5_and_7_long_axes_match_oracle(shape, prec):
+    """The paper's 896-node transverse axes (Sec. III.A, Fig. 4) and other
+    5- and 7-smooth lengths on every axis, two steps against the oracle."""
+    g, st = transverse_state(95 + shape[1], shape, 0.23)
+    if prec == "f32":
+        st = st.astype(np.float32).astype(np.float64)
+    out, _ = run_gpu(g, prec, st, 2, 0.47)
+    Eo, Bo = psatd.step_fft(st[:3], st[3:], spacing(g), 0.47, nsteps=2)
+    tol = 1e-11 if prec == "f64" else 2 * F32_TOL
+    assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= tol
+
+
 def test_determinism_bitwise():
     g, st = transverse_state(23, (64, 64, 64), 0.25)
     a, _ = run_gpu(g, "f32", st.astype(np.float32), 3, 0.4)

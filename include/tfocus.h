@@ -249,6 +249,19 @@ tf_status tf_read_focal(tf_solver* s, const tf_window* win, void* dst, int32_t d
  * not finite. */
 tf_status tf_diagnostics(tf_solver* s, double* energy, double* max_div_e, double* max_div_b);
 
+/* tf_advance followed by tf_diagnostics without the diagnostics' own
+ * passes: nsteps >= 1 steps of dt, the last of which runs the generic z
+ * kernel with the diagnostics folded into it (Sec. II.A: the energy the
+ * rotation of Eqs. (3)-(4) conserves, and the transversality the text after
+ * Eq. (2) asks for).  The values describe the state after the call, taken
+ * from its spectrum inside that z pass: energy by Parseval (the R2C half
+ * spectrum with weight 2 off the packed kx = 0 slot), the same ratios as
+ * tf_diagnostics (equal to it up to rounding).  Synchronous.  Any output
+ * pointer may be NULL.  TF_EINVAL for nsteps < 1; TF_ENONFINITE if the
+ * energy is not finite. */
+tf_status tf_advance_diagnosed(tf_solver* s, int64_t nsteps, double dt, double* energy, double* max_div_e,
+                               double* max_div_b);
+
 /* Current time t (host bookkeeping, no synchronisation). */
 tf_status tf_time(const tf_solver* s, double* t);
 

@@ -36,7 +36,7 @@ struct StepParams {
     int zvariant;            // shape of the fused float32 z kernel (strip modes, elements per lane, first radix)
 };
 
-enum ZMode { Z_STEP = 0, Z_DIAG = 1 };
+enum ZMode { Z_STEP = 0, Z_DIAG = 1, Z_STEP_DIAG = 2 };
 
 // Launch over n same-shape instances (grid y): instance i's state and
 // spectrum start sreal resp. sspec elements (of the element type resp.
@@ -63,7 +63,11 @@ template <typename T> hipError_t launch_y_pass(void* spec, const void* tw, int n
 // Z_DIAG = forward z FFT and per-block maxima |k.E|, |k.B|, |E|, |B| into
 // partials (4 doubles per block; the packed kx = 0 slot goes through dc, a
 // buffer of ny nz 6 complex elements), no store.  *nblocks receives the
-// number of 4-wide partials written.
+// number of 4-wide partials written.  Z_STEP_DIAG = Z_STEP (generic kernel)
+// whose blocks also take the diagnostics of the updated spectrum (the next
+// state, scaled by 1/(nx ny nz)): the 4-wide maxima as Z_DIAG, then after
+// the 4 *nblocks maxima one weighted sum of |coefficient|^2 per z block
+// (*nblocks - ny of them; Parseval energy up to the factor nx ny nz).
 template <typename T> hipError_t launch_z_pass(void* spec, const void* tw, const StepParams& p,
                                                RowMap rm, int mode, double* partials, void* dc,
                                                int* nblocks, bool fast, Batch bt, hipStream_t st);

@@ -133,13 +133,19 @@ hipError_t current_step(tf_solver* s, double dt, bool project_b) {
     });
 }
 
+// One step; with diag_blocks the z pass is the generic kernel that also
+// writes the diagnostics of the new state into s->partials (Z_STEP_DIAG),
+// and *diag_blocks receives its count of 4-wide partials.
 template <typename T>
-hipError_t one_step(tf_solver* s, double dt, bool project_b) {
+hipError_t one_step(tf_solver* s, double dt, bool project_b, int* diag_blocks = nullptr) {
     const tf_grid& g = s->grid;
     hipError_t e = forward_xy<T>(s, TF_PASS_X_FORWARD, TF_PASS_Y_FORWARD);
     if (e != hipSuccess) return e;
     tf::StepParams p = step_params(s->grid, dt, project_b, s->zvariant);
     e = timed(s, TF_PASS_Z_STEP, [&] {
+        if (diag_blocks)
+            return tf::launch_z_pass<T>(s->spec, s->tw[2], p, s->rm, tf::Z_STEP_DIAG, s->partials, s->dcbuf,
+                                        diag_blocks, false, tf::Batch{}, s->stream);
         return tf::launch_z_pass<T>(s->spec, s->tw[2], p, s->rm, tf::Z_STEP, nullptr, nullptr, nullptr, s->fast,
                                     tf::Batch{}, s->stream);
     });
@@ -362,7 +368,7 @@ tf_status tf_create(const tf_grid* grid, int32_t precision, void* hip_stream, tf
     const size_t spec_b = (size_t)grid->nz * grid->ny * s->nkx * 6 * 2 * s->esize;
     const int zb = precision == TF_F64 ? tf::z_diag_blocks<double>(grid->nx, grid->ny, grid->nz)
                                        : tf::z_diag_blocks<float>(grid->nx, grid->ny, grid->nz);
-    s->npartials = std::max<size_t>(tf::SUMSQ_BLOCKS, (size_t)zb * 4);
+    s->npartials = std::max<size_t>(tf::SUMSQ_BLOCKS, (size_t)zb * 5);
     const size_t tw_b = 2 * s->esize * (size_t)(grid->nx + grid->ny + grid->nz);
     const size_t dc_b = (size_t)grid->ny * grid->nz * 6 * 2 * s->esize;
     const size_t need = state_b + spec_b + tw_b + dc_b + s->npartials * 8 + 64;
@@ -646,6 +652,37 @@ tf_status tf_diagnostics(tf_solver* s, double* energy, double* max_div_e, double
     if (max_div_e) *max_div_e = h[3] > 0.0 ? h[1] / h[3] : 0.0;
     if (max_div_b) *max_div_b = h[4] > 0.0 ? h[2] / h[4] : 0.0;
     if (!std::isfinite(h[0])) return fail(TF_ENONFINITE, "field energy is not finite");
+    return TF_OK;
+}
+
+tf_status tf_advance_diagnosed(tf_solver* s, int64_t nsteps, double dt, double* energy, double* max_div_e,
+                               double* max_div_b) {
+    if (!s) return fail(TF_EINVAL, "solver is NULL");
+    if (nsteps < 1) return fail(TF_EINVAL, "nsteps must be >= 1");
+    if (!std::isfinite(dt)) return fail(TF_EINVAL, "dt must be finite");
+    if (nsteps > 1) {
+        tf_status st = tf_advance(s, nsteps - 1, dt);
+        if (st != TF_OK) return st;
+    }
+    int nb = 0;
+    const bool pb = s->project_b_next;
+    hipError_t e = s->prec == TF_F64 ? one_step<double>(s, dt, pb, &nb) : one_step<float>(s, dt, pb, &nb);
+    if (e != hipSuccess) return fail(TF_EDEVICE, std::string("diagnosed step: ") + hipGetErrorString(e));
+    s->project_b_next = false;
+    s->t = s->t + dt;
+    const int nz_blocks = nb - s->grid.ny;
+    e = tf::launch_reduce(s->partials + 4L * nb, nz_blocks, 1, 0, 0, s->results, s->stream);
+    for (int q = 0; q < 4 && e == hipSuccess; ++q) e = tf::launch_reduce(s->partials, nb, 4, q, 1, s->results + 1 + q, s->stream);
+    double h[5] = {0, 0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(h, s->results, sizeof(h), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return fail(TF_EDEVICE, std::string("diagnostics: ") + hipGetErrorString(e));
+    // Parseval: the updated coefficients carry the 1/(nx ny nz) of the inverse transform
+    const double en = h[0] * (double)s->cells;
+    if (energy) *energy = en;
+    if (max_div_e) *max_div_e = h[3] > 0.0 ? h[1] / h[3] : 0.0;
+    if (max_div_b) *max_div_b = h[4] > 0.0 ? h[2] / h[4] : 0.0;
+    if (!std::isfinite(en)) return fail(TF_ENONFINITE, "field energy is not finite");
     return TF_OK;
 }
 

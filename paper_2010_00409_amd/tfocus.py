@@ -87,6 +87,8 @@ _SIGS = {
     "tf_read_focal": ([_P, ctypes.POINTER(tf_window), _P, ctypes.c_int32], ctypes.c_int),
     "tf_diagnostics": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                         ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "tf_advance_diagnosed": ([_P, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "tf_time": ([_P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "tf_get_grid": ([_P, ctypes.POINTER(tf_grid)], ctypes.c_int),
     "tf_batch_create": ([ctypes.POINTER(tf_grid), ctypes.POINTER(tf_pulse), ctypes.c_int32, ctypes.c_int32, _P,
@@ -317,6 +319,15 @@ def tf_diagnostics(h):
     return e.value, de.value, db.value
 
 
+def tf_advance_diagnosed(h, nsteps, dt):
+    """nsteps steps of dt; (energy, max_div_e, max_div_b) of the new state
+    from the last step's z pass."""
+    e, de, db = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(load().tf_advance_diagnosed(h, int(nsteps), float(dt), ctypes.byref(e), ctypes.byref(de),
+                                       ctypes.byref(db)))
+    return e.value, de.value, db.value
+
+
 def tf_time(h):
     t = ctypes.c_double()
     _check(load().tf_time(h, ctypes.byref(t)))
@@ -504,6 +515,9 @@ class Solver:
 
     def diagnostics(self):
         return tf_diagnostics(self.h)
+
+    def advance_diagnosed(self, nsteps, dt):
+        return tf_advance_diagnosed(self.h, nsteps, dt)
 
     @property
     def t(self):

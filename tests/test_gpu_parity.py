@@ -219,6 +219,53 @@ def test_diagnostics_energy_and_divergence():
         assert de == pytest.approx(rde, rel=1e-10) and db == pytest.approx(rdb, rel=1e-10)
 
 
+def test_diagnostics_fused_into_the_last_step_f64():
+    """tf_advance_diagnosed: the energy (Parseval on the updated spectrum)
+    and the divergence ratios of the state after the steps, against the
+    oracle's state and tf_diagnostics, for fields with longitudinal parts
+    (B's survives the steps, E's is removed)."""
+    g = dict(nx=24, ny=40, nz=32, dx=0.3, dy=0.25, dz=0.2, x_min=0.0, y_min=0.0, z_min=0.0)
+    x = np.random.default_rng(8).standard_normal((6, 32, 40, 24))
+    Eo, Bo = psatd.step_fft(x[:3], x[3:], spacing(g), 0.4, nsteps=3)
+    with tf.Solver(g, "f64") as s:
+        s.set_fields(x)
+        en, de, db = s.advance_diagnosed(3, 0.4)
+        out = np.empty(s.shape)
+        s.get_fields(out)
+        en2, de2, db2 = s.diagnostics()
+        assert s.t == pytest.approx(1.2)
+    assert rel(out, np.concatenate([Eo, Bo])) <= F64_TOL
+    assert en == pytest.approx(psatd.energy(Eo, Bo), rel=1e-12)
+    assert en == pytest.approx(en2, rel=1e-12)
+    rde, rdb = psatd.max_divergence(Eo, Bo, spacing(g))
+    assert rdb > 0.1 and db == pytest.approx(rdb, rel=1e-9) and db == pytest.approx(db2, rel=1e-9)
+    assert de < 1e-13 and de2 < 1e-13 and rde < 1e-13
+    with tf.Solver(g, "f64") as s:
+        with pytest.raises(tf.TfError) as ei:
+            s.advance_diagnosed(0, 0.4)
+        assert ei.value.status == tf.TF_EINVAL
+
+
+@pytest.mark.parametrize("shape", [(128, 128, 128), (512, 32, 64)])
+def test_diagnostics_fused_into_the_last_step_f32(shape):
+    """Float32 plans with fast kernels: the diagnosed step runs the generic z
+    kernel; the state matches the oracle and the diagnostics those of
+    tf_diagnostics on the same state and the oracle's energy."""
+    g, st = transverse_state(31 + shape[0], shape, 0.27)
+    st = st.astype(np.float32).astype(np.float64)
+    Eo, Bo = psatd.step_fft(st[:3], st[3:], spacing(g), 0.35, nsteps=10)
+    with tf.Solver(g, "f32") as s:
+        s.set_fields(st.astype(np.float32))
+        en, de, db = s.advance_diagnosed(10, 0.35)
+        out = np.empty(s.shape, np.float32)
+        s.get_fields(out)
+        en2, de2, db2 = s.diagnostics()
+    assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= 10 * F32_TOL
+    assert en == pytest.approx(en2, rel=1e-5)
+    assert en == pytest.approx(psatd.energy(Eo, Bo), rel=1e-5)
+    assert de < 1e-5 and db < 1e-5 and de2 < 1e-5 and db2 < 1e-5
+
+
 def test_reversibility_and_semigroup_on_gpu_f32():
     g, st = transverse_state(22, (64, 64, 64), 0.25)
     st = st.astype(np.float32)

@@ -552,10 +552,10 @@ tf_status tf_tune(const int32_t* sizes, int32_t n, int32_t precision, const char
             p.fast = false;
             cands.push_back(p);
             if (!fast_offsets_fit(g, rb, precision)) continue;
-            // variants 7 and 8 (one wave per mode) exist for 512-point z
+            // variants 7 to 9 (one wave per mode) exist for 512-point z
             // columns; elsewhere they run variant 6
             for (int ys : {64, 32})
-                for (int zv = 0; zv < (N == 512 ? 9 : 7); ++zv) {
+                for (int zv = 0; zv < (N == 512 ? 10 : 7); ++zv) {
                     p.fast = true;
                     p.zvariant = zv;
                     p.ystrip = ys;

@@ -319,7 +319,7 @@ def test_graph_replayed_steps_equal_eager_steps_bitwise(prec):
     assert rel(outs[1][0].astype(np.float64), np.concatenate([Eo, Bo])) <= tol
 
 
-@pytest.mark.parametrize("zvariant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("zvariant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_every_z_variant_at_length_512(zvariant, monkeypatch):
     """512-point z columns (where variants 5 and 6 differ, residues are
     parked in LDS or held in registers, and variants 7 and 8 run one wave per
@@ -332,7 +332,7 @@ def test_every_z_variant_at_length_512(zvariant, monkeypatch):
     assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= 2 * F32_TOL
 
 
-@pytest.mark.parametrize("zvariant", [7, 8])
+@pytest.mark.parametrize("zvariant", [7, 8, 9])
 def test_wave_z_kernel_projection_and_huge_phases(zvariant, monkeypatch):
     """The one-wave-per-mode z kernel on 512-point columns: the first step
     after tf_set_pulse (which also removes longitudinal B) against the

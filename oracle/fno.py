@@ -25,6 +25,13 @@ polarisation (oracle.pulse.phasor_weights).
 Kept modes: kx in [0, M) on the rfft axis, ky and kz in [0, M) U [N-M, N)
 (the usual truncation; the set is not closed under negation, so in the
 kx = 0 plane the index N-M has no kept partner).
+Padded spectral transform (period P > N, ``HP.period``): v is extended by
+zeros to a P^3 block, rfftn and irfftn run with period P (kept modes
+[0, M) U [P-M, P) along y and z, [0, M) along x), and the inverse is cut
+back to the N^3 window: u = crop(irfftn_P(Yh)).  A window whose fields do
+not match across opposite faces is then not forced into an N-periodic
+band-limited form (the usual padding of Fourier neural operators on
+non-periodic domains).  P = N is the plain transform.
 Mode order q = (kz_i * 2M + ky_i) * M + kx, ky_i / kz_i indexing the kept
 list ascending.  GELU(x) = x (1 + erf(x / sqrt 2)) / 2.
 Loss of a batch: mean over samples of ||out - y|| / ||y||.
@@ -47,10 +54,12 @@ import scipy.special
 
 
 class HP:
-    def __init__(self, n=64, width=32, modes=12, nparam=8, hidden=128, nout=6, layers=3, nbasis=1):
+    def __init__(self, n=64, width=32, modes=12, nparam=8, hidden=128, nout=6, layers=3, nbasis=1, period=None):
         self.n, self.width, self.modes = n, width, modes
         self.nparam, self.hidden, self.nout, self.layers = nparam, hidden, nout, layers
         self.nbasis = nbasis
+        self.period = n if period is None else int(period)
+        assert self.period >= n
 
     @property
     def nmodes(self):
@@ -59,8 +68,8 @@ class HP:
 
 def kept_index(hp):
     """Arrays (kz, ky, kx) of the kept modes in the canonical order."""
-    M, N = hp.modes, hp.n
-    side = np.concatenate([np.arange(M), np.arange(N - M, N)])
+    M, P = hp.modes, hp.period
+    side = np.concatenate([np.arange(M), np.arange(P - M, P)])
     kz, ky, kx = np.meshgrid(side, side, np.arange(M), indexing="ij")
     return kz.ravel(), ky.ravel(), kx.ravel()
 
@@ -95,19 +104,22 @@ def gelu_grad(x):
 
 
 def spectral_forward(v, hp):
-    """v: (B, C, N, N, N) real -> kept rfftn coefficients (B, C, nmodes)."""
+    """v: (B, C, N, N, N) real -> kept rfftn coefficients (B, C, nmodes) of
+    v extended by zeros to the period P."""
+    P = hp.period
     kz, ky, kx = kept_index(hp)
-    Xf = scipy.fft.rfftn(v, axes=(2, 3, 4))
+    Xf = scipy.fft.rfftn(v, s=(P, P, P), axes=(2, 3, 4))
     return Xf[:, :, kz, ky, kx]
 
 
 def spectral_inverse(Yh, hp):
-    """Kept coefficients (B, C, nmodes) -> irfftn with zeros elsewhere."""
-    N = hp.n
+    """Kept coefficients (B, C, nmodes) -> irfftn of period P with zeros
+    elsewhere, cut to the N^3 window."""
+    N, P = hp.n, hp.period
     kz, ky, kx = kept_index(hp)
-    full = np.zeros(Yh.shape[:2] + (N, N, N // 2 + 1), dtype=np.complex128)
+    full = np.zeros(Yh.shape[:2] + (P, P, P // 2 + 1), dtype=np.complex128)
     full[:, :, kz, ky, kx] = Yh
-    return scipy.fft.irfftn(full, s=(N, N, N), axes=(2, 3, 4))
+    return scipy.fft.irfftn(full, s=(P, P, P), axes=(2, 3, 4))[:, :, :N, :N, :N]
 
 
 def _mult(hp):
@@ -195,7 +207,7 @@ def loss_and_grad(P, pb, y, hp, w=None):
     G["P1"] = _outer(c["vL"], g_hpre)
     G["c1"] = g_hpre.sum(axis=(0, 2, 3, 4))
     g_v = np.einsum("bo...,io->bi...", g_hpre, P["P1"])
-    N3 = float(hp.n) ** 3
+    N3 = float(hp.period) ** 3
     m = _mult(hp)
     for l in reversed(range(hp.layers)):
         z = c[f"z{l}"]
@@ -204,12 +216,12 @@ def loss_and_grad(P, pb, y, hp, w=None):
         G[f"W{l + 1}"] = _outer(v, g_z)
         G[f"b{l + 1}"] = g_z.sum(axis=(0, 2, 3, 4))
         g_v = np.einsum("bo...,io->bi...", g_z, P[f"W{l + 1}"])
-        # u = irfftn(Yh): dL/dYh = (m / N^3) rfftn(g_u) on the kept modes
+        # u = irfftn(Yh): dL/dYh = (m / P^3) rfftn(g_u) on the kept modes
         g_Y = spectral_forward(g_z, hp) * (m / N3)
         Xh = c[f"X{l}"]
         G[f"R{l + 1}"] = np.einsum("bcq,boq->qco", np.conj(Xh), g_Y)
         g_X = np.einsum("boq,qco->bcq", g_Y, np.conj(P[f"R{l + 1}"]))
-        # Xh = rfftn(v)[modes]: dL/dv = Re sum g_X e^{+ik.x} = N^3 irfftn(g_X / m)
+        # Xh = rfftn(v)[modes]: dL/dv = Re sum g_X e^{+ik.x} = P^3 irfftn(g_X / m)
         g_v = g_v + spectral_inverse(g_X / m, hp) * N3
     G["W0"] = _outer(c["a"], g_v)
     G["b0"] = g_v.sum(axis=(0, 2, 3, 4))

@@ -8,13 +8,13 @@ import pytest
 from oracle import fno
 
 
-def tiny(nbasis=1):
-    return fno.HP(n=8, width=4, modes=2, nparam=8, hidden=6, nout=6, layers=3, nbasis=nbasis)
+def tiny(nbasis=1, period=None):
+    return fno.HP(n=8, width=4, modes=2, nparam=8, hidden=6, nout=6, layers=3, nbasis=nbasis, period=period)
 
 
-@pytest.mark.parametrize("nbasis", [1, 4])
-def test_gradients_match_central_differences(nbasis):
-    hp = tiny(nbasis)
+@pytest.mark.parametrize("nbasis, period", [(1, None), (4, None), (4, 11)])
+def test_gradients_match_central_differences(nbasis, period):
+    hp = tiny(nbasis, period)
     P = fno.init_params(1, hp)
     for k in list(P):
         if k.startswith("b") or k.startswith("c"):
@@ -65,6 +65,38 @@ def test_spectral_branch_is_translation_equivariant():
     f = lambda w: fno.spectral_inverse(np.einsum("bcq,qco->boq", fno.spectral_forward(w, hp), P["R1"]), hp)
     sh = lambda w: np.roll(w, (2, -3, 5), axis=(2, 3, 4))
     assert np.abs(f(sh(v)) - sh(f(v))).max() < 1e-12
+
+
+def test_padded_transform_is_translation_equivariant_inside_the_window():
+    """Period P > N: the spectral branch is a convolution on the P-periodic
+    torus of the zero-extended input, cut to the window, so moving an input
+    supported away from the window's far faces by s nodes moves the output
+    by s at every window node that stays inside (x - s >= 0).  It is also
+    the plain branch on a P^3 grid (pinned by the band-limited reproduction
+    above) applied to the input extended by zeros at the far faces and cut
+    back to the window's corner, which a wrong period, padding or cut would
+    break."""
+    hp = fno.HP(n=16, width=3, modes=3, period=22)
+    P = fno.init_params(4, hp)
+    v = np.zeros((1, 3, 16, 16, 16))
+    v[:, :, :11, :12, :10] = np.random.default_rng(5).normal(size=(1, 3, 11, 12, 10))
+    f = lambda w: fno.spectral_inverse(np.einsum("bcq,qco->boq", fno.spectral_forward(w, hp), P["R1"]), hp)
+    s = (2, 3, 5)
+    vs = np.zeros_like(v)
+    vs[:, :, s[0]:, s[1]:, s[2]:] = v[:, :, :16 - s[0], :16 - s[1], :16 - s[2]]
+    a, b = f(vs), f(v)
+    assert np.abs(a[:, :, s[0]:, s[1]:, s[2]:] - b[:, :, :16 - s[0], :16 - s[1], :16 - s[2]]).max() < 1e-12 * np.abs(b).max()
+    big = fno.HP(n=22, width=3, modes=3)
+    ext = np.zeros((1, 3, 22, 22, 22))
+    ext[:, :, :16, :16, :16] = v
+    g = fno.spectral_inverse(np.einsum("bcq,qco->boq", fno.spectral_forward(ext, big), P["R1"]), big)
+    assert np.abs(g[:, :, :16, :16, :16] - b).max() < 1e-12 * np.abs(b).max()
+
+
+def test_padded_transform_of_period_n_is_the_plain_one():
+    hp, hq = fno.HP(n=8, width=2, modes=2), fno.HP(n=8, width=2, modes=2, period=8)
+    v = np.random.default_rng(6).normal(size=(1, 2, 8, 8, 8))
+    assert np.array_equal(fno.spectral_forward(v, hp), fno.spectral_forward(v, hq))
 
 
 def test_phasor_head_is_the_plain_head_when_the_weights_select_one_group():

@@ -95,7 +95,7 @@ void load_plans_locked() {
 void env_overrides(const tf_grid& g, KernelPlan& p) {
     if (const char* v = std::getenv("TFOCUS_ROW_BLOCK")) {
         const int b = std::atoi(v);
-        if (b > 0 && g.ny % b == 0) p.row_block = b;
+        if (tf::row_block_ok(b, g.ny)) p.row_block = b;
     }
     if (const char* v = std::getenv("TFOCUS_GENERIC_KERNELS")) p.fast = !(v[0] == '1');
     if (const char* v = std::getenv("TFOCUS_ZVARIANT")) p.zvariant = std::atoi(v);
@@ -122,7 +122,7 @@ tf::host::KernelPlan tf::host::plan_for(const tf_grid& g, int precision) {
             load_plans_locked();
             const PlanKey k{device_arch(), precision, g.nx, g.ny, g.nz};
             auto it = g_plans.find(k);
-            if (it != g_plans.end() && g.ny % it->second.row_block == 0) p = it->second;
+            if (it != g_plans.end() && tf::row_block_ok(it->second.row_block, g.ny)) p = it->second;
         }
     }
     env_overrides(g, p);
@@ -356,9 +356,7 @@ tf_status tf_batch_create(const tf_grid* grids, const tf_pulse* pulses, int32_t 
         G.state_elems = 6 * (size_t)G.cells;
         G.spec_elems = 2 * 6 * (size_t)g.nz * g.ny * tf::nkx_of(g.nx);
         G.kp = plan_for(g, precision);
-        G.rm.ny = g.ny;
-        G.rm.nz = g.nz;
-        G.rm.G = G.kp.row_block;
+        G.rm = tf::RowMap(g.ny, g.nz, G.kp.row_block);
         const size_t m = G.members.size();
         st = alloc(&G.state, m * G.state_elems * b->esize);
         if (st == TF_OK) st = alloc(&G.spec, m * G.spec_elems * b->esize);

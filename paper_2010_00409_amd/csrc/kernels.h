@@ -20,12 +20,33 @@ inline bool z_fast_offsets_fit(int nx, int nz, int G, size_t complex_bytes) {
     return ((unsigned long long)(nz - 1) * (unsigned long long)G + 1ull) * rowb <= (1ull << 32);
 }
 
+// Row of (kz, ky) in the spectral array: G = ny keeps rows in natural
+// order (kz major); otherwise G, a power of two dividing ny, blocks ky by G
+// (rows [ky / G][kz][ky % G]).  The passes compute a row for every element
+// they move, so the row is a shift and two masks set up on the host, with
+// no division and no branch: ky / G = (ky >> sh) & qmask, ky % G = ky & rmask
+// (unblocked: qmask = 0, rmask = all ones).
 struct RowMap {
-    int ny, nz, G;
+    int ny = 0, nz = 0, G = 0;
+    int sh = 0, qmask = 0, rmask = 0;
+    RowMap() = default;
+    __host__ __device__ RowMap(int ny_, int nz_, int G_) : ny(ny_), nz(nz_), G(G_) {
+        if (G >= ny) {
+            sh = 0; qmask = 0; rmask = -1;
+        } else {
+            while ((1 << sh) < G) ++sh;
+            qmask = -1; rmask = G - 1;
+        }
+    }
     __host__ __device__ __forceinline__ long row(int z, int y) const {
-        return ((long)(y / G) * nz + z) * G + (y % G);
+        return ((long)((y >> sh) & qmask) * nz + z) * G + (y & rmask);
     }
 };
+
+// Row blockings RowMap supports for an axis of ny: ny itself or a power of two dividing ny.
+inline bool row_block_ok(int G, int ny) {
+    return G == ny || (G > 0 && (G & (G - 1)) == 0 && ny % G == 0);
+}
 
 struct StepParams {
     int nx, ny, nz, nkx;

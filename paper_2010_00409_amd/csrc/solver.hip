@@ -373,9 +373,7 @@ tf_status tf_create(const tf_grid* grid, int32_t precision, void* hip_stream, tf
     const size_t dc_b = (size_t)grid->ny * grid->nz * 6 * 2 * s->esize;
     const size_t need = state_b + spec_b + tw_b + dc_b + s->npartials * 8 + 64;
     const KernelPlan kp = plan_for(*grid, precision);
-    s->rm.ny = grid->ny;
-    s->rm.nz = grid->nz;
-    s->rm.G = kp.row_block;
+    s->rm = tf::RowMap(grid->ny, grid->nz, kp.row_block);
     s->fast = kp.fast;
     s->zvariant = kp.zvariant;
     s->ystrip = kp.ystrip;

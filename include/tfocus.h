@@ -423,6 +423,19 @@ tf_status tf_fno_phasor_weights(const tf_pulse* pulse, int32_t nbasis, double* w
  * activations, gradients and Adam state (about 0.45 GB per sample plus
  * 0.8 GB).  Parameters start at 0. */
 tf_status tf_fno_create(int32_t max_batch, int32_t training, int32_t nbasis, void* hip_stream, tf_fno** out);
+
+/* Period P of the surrogate's spectral transform, 64 (the plain transform
+ * over the 64^3 window, the default) to 256.  With P > 64 the window is
+ * extended by zeros to P nodes per axis, the kept modes are those of the
+ * period-P transform ([0, 12) along x, [0, 12) U [P - 12, P) along y and
+ * z) and the inverse is cut back to the window: the usual padding of
+ * Fourier neural operators, for windows whose fields do not match across
+ * opposite faces.  Only the truncated-DFT tables change (rebuilt in float64
+ * and uploaded, synchronously); weights, shapes and kernels stay.  Changing
+ * the period changes what existing weights compute.  TF_EINVAL outside
+ * [64, 256]. */
+tf_status tf_fno_set_period(tf_fno* f, int32_t period);
+tf_status tf_fno_get_period(const tf_fno* f, int32_t* period);
 tf_status tf_fno_destroy(tf_fno* f);
 
 /* Copy the flat parameter vector in or out.  Setting resets Adam. */
@@ -465,6 +478,10 @@ typedef struct {
     int32_t reserved;
     double* epoch_loss;      /* host, nullable: epochs entries, the mean batch loss
                                 of each epoch                                          */
+    void (*progress)(int32_t epoch, double loss, void* user);
+                             /* nullable: called on the calling thread after each
+                                epoch with its mean loss (for logs of long runs)      */
+    void* progress_user;     /* passed to progress                                   */
 } tf_train_cfg;
 
 /* A whole training run on the device: per epoch a Fisher-Yates shuffle of the
@@ -492,8 +509,9 @@ tf_status tf_fno_spectral_forward(tf_fno* f, const float* v, int32_t batch, floa
 tf_status tf_fno_spectral_inverse(tf_fno* f, const float* modes, int32_t batch, float* u);
 
 /* Checkpoint the float32 parameters (and, for a training surrogate, the Adam
- * moments and step) to a file, and read one back.  TF_EINVAL for a file of
- * another architecture or head. */
+ * moments and step) to a file, and read one back.  A surrogate with a
+ * padded transform records its period, and loading restores it.  TF_EINVAL
+ * for a file of another architecture or head. */
 tf_status tf_fno_save(tf_fno* f, const char* path);
 tf_status tf_fno_load(tf_fno* f, const char* path);
 

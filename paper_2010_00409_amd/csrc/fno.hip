@@ -1153,16 +1153,20 @@ inline Result res(float* p, Ix r, Ix c, int64_t b1, int64_t b2, float alpha = 1.
     return Result{p, b1, b2, r, c, alpha, acc};
 }
 
-// DFT tables, float64-built from the exact integer phase (j k mod 64)
+// DFT tables, float64-built from the exact integer phase (j k mod P), for
+// the spectral transform of period P >= N: the window extended by zeros to
+// P nodes per axis, the kept modes [0, M) (x) and [0, M) U [P - M, P) (y, z)
+// of the period-P DFT, and the inverse's 1/P per axis, cut back to the N
+// window nodes.  P = N is the plain transform; the backward passes use the
+// transposed tables, so they are the exact adjoints for any P.
 struct Tables {
     std::vector<float> fx, fxT, gx, gxT, fs, fsT, gs, gsT;
 };
 
-inline int side(int i) { return i < M ? i : N - 2 * M + i; }
-
-inline Tables build_tables() {
+inline Tables build_tables(int P) {
     Tables t;
-    auto ang = [](int a, int b) { return 2.0 * M_PI * double((int64_t(a) * b) % N) / N; };
+    auto ang = [P](int a, int b) { return 2.0 * M_PI * double((int64_t(a) * b) % P) / P; };
+    auto side = [P](int i) { return i < M ? i : P - 2 * M + i; };
     t.fx.assign(24 * N, 0.f);
     t.gx.assign(N * 24, 0.f);
     for (int kx = 0; kx < M; ++kx)
@@ -1170,8 +1174,8 @@ inline Tables build_tables() {
             const double th = ang(kx, x), mult = kx == 0 ? 1.0 : 2.0;
             t.fx[(0 * M + kx) * N + x] = float(std::cos(th));
             t.fx[(1 * M + kx) * N + x] = float(-std::sin(th));
-            t.gx[x * 24 + 0 * M + kx] = float(mult / N * std::cos(th));
-            t.gx[x * 24 + 1 * M + kx] = float(-mult / N * std::sin(th));
+            t.gx[x * 24 + 0 * M + kx] = float(mult / P * std::cos(th));
+            t.gx[x * 24 + 1 * M + kx] = float(-mult / P * std::sin(th));
         }
     t.fs.assign(48 * 128, 0.f);
     t.gs.assign(128 * 48, 0.f);
@@ -1179,7 +1183,7 @@ inline Tables build_tables() {
         for (int n = 0; n < N; ++n) {
             const double th = ang(side(ki), n);
             const double fr = std::cos(th), fi = -std::sin(th);       // e^{-i th}
-            const double gr = std::cos(th) / N, gi = std::sin(th) / N; // e^{+i th} / N
+            const double gr = std::cos(th) / P, gi = std::sin(th) / P; // e^{+i th} / P
             // forward block [[fr, -fi], [fi, fr]] at (row (ki, s'), col (n, s))
             t.fs[(2 * ki + 0) * 128 + 2 * n + 0] = float(fr);
             t.fs[(2 * ki + 0) * 128 + 2 * n + 1] = float(-fi);
@@ -1232,6 +1236,8 @@ struct tf_fno {
     bf16 *wb[LAYERS] = {}, *rb[LAYERS] = {}, *p1b = nullptr, *p2e = nullptr, *p1k = nullptr, *p2k = nullptr;
     float *c2e = nullptr, *geff = nullptr;
     float *fx, *fxT, *gx, *gxT, *fs, *fsT, *gs, *gsT;
+    float* tab = nullptr;       // the eight tables, one allocation
+    int period = N;             // period of the spectral transform (tables built for it)
     float* V[4] = {};
     float* Z[2] = {};
     float* X3[LAYERS] = {};
@@ -1392,6 +1398,37 @@ tf_status tf_fno_phasor_weights(const tf_pulse* pulse, int32_t nbasis, double* w
     return TF_OK;
 }
 
+// Builds the DFT tables of period P and copies them into f->tab (synchronous).
+static tf_status upload_tables(tf_fno* f, int P) {
+    Tables t = build_tables(P);
+    std::vector<float> all;
+    auto put = [&](const std::vector<float>& v, float** p) {
+        *p = f->tab + all.size();
+        all.insert(all.end(), v.begin(), v.end());
+    };
+    put(t.fx, &f->fx); put(t.fxT, &f->fxT); put(t.gx, &f->gx); put(t.gxT, &f->gxT);
+    put(t.fs, &f->fs); put(t.fsT, &f->fsT); put(t.gs, &f->gs); put(t.gsT, &f->gsT);
+    TF_HIP(hipMemcpyAsync(f->tab, all.data(), all.size() * sizeof(float), hipMemcpyHostToDevice, f->st));
+    TF_HIP(hipStreamSynchronize(f->st));
+    f->period = P;
+    return TF_OK;
+}
+
+tf_status tf_fno_set_period(tf_fno* f, int32_t period) {
+    if (!f) return fail(TF_EINVAL, "NULL argument");
+    if (period < N || period > 4 * N) return fail(TF_EINVAL, "period must be in [64, 256]");
+    if (period == f->period) return TF_OK;
+    TF_HIP(hipSetDevice(f->dev));
+    TF_HIP(hipStreamSynchronize(f->st));
+    return upload_tables(f, period);
+}
+
+tf_status tf_fno_get_period(const tf_fno* f, int32_t* period) {
+    if (!f || !period) return fail(TF_EINVAL, "NULL argument");
+    *period = f->period;
+    return TF_OK;
+}
+
 tf_status tf_fno_create(int32_t max_batch, int32_t training, int32_t nbasis, void* hip_stream, tf_fno** out) {
     if (!out) return fail(TF_EINVAL, "out is NULL");
     *out = nullptr;
@@ -1422,18 +1459,9 @@ tf_status tf_fno_create(int32_t max_batch, int32_t training, int32_t nbasis, voi
     TRY(f->alloc(&f->p2k, B * KSLOTS));
     TF_HIP(hipMemset(f->p2k, 0, B * KSLOTS * sizeof(bf16)));     // rows t >= 6 stay 0
 
-    Tables t = build_tables();
-    float* tab = nullptr;
     const int64_t ntab = 4 * 24 * N + 4 * 48 * 128;
-    TRY(f->alloc(&tab, ntab));
-    std::vector<float> all;
-    auto put = [&](const std::vector<float>& v, float** p) {
-        *p = tab + all.size();
-        all.insert(all.end(), v.begin(), v.end());
-    };
-    put(t.fx, &f->fx); put(t.fxT, &f->fxT); put(t.gx, &f->gx); put(t.gxT, &f->gxT);
-    put(t.fs, &f->fs); put(t.fsT, &f->fsT); put(t.gs, &f->gs); put(t.gsT, &f->gsT);
-    TF_HIP(hipMemcpy(tab, all.data(), all.size() * sizeof(float), hipMemcpyHostToDevice));
+    TRY(f->alloc(&f->tab, ntab));
+    TRY(upload_tables(f.get(), N));
 
     TRY(f->alloc(&f->V[0], B * NODE_SZ));
     TRY(f->alloc(&f->V[1], B * NODE_SZ));
@@ -1875,6 +1903,7 @@ tf_status tf_fno_train(tf_fno* f, const float* params, const float* head_w, cons
         for (double v : hlog) m += v;
         last = m / double(spe);
         if (cfg->epoch_loss) cfg->epoch_loss[ep] = last;
+        if (cfg->progress) cfg->progress(int32_t(ep), last, cfg->progress_user);
         if (!std::isfinite(last)) return fail(TF_ENONFINITE, "training loss is not finite");
     }
     if (cfg->scale_targets) {
@@ -1947,8 +1976,11 @@ tf_status tf_fno_save(tf_fno* f, const char* path) {
     std::vector<float> h(NPARAMS);
     FILE* fp = std::fopen(path, "wb");
     if (!fp) return fail(TF_EINVAL, std::string("cannot open ") + path);
-    const int64_t hdr[4] = {0x4f4e4646554354LL, 1, NPARAMS, f->training ? f->adam_t : -1};
-    bool ok = std::fwrite(hdr, sizeof(hdr), 1, fp) == 1;
+    // version 1: the plain transform; version 2 adds the period of the
+    // spectral transform as a fifth header word
+    const int64_t hdr[5] = {0x4f4e4646554354LL, f->period == N ? 1 : 2, NPARAMS, f->training ? f->adam_t : -1,
+                            f->period};
+    bool ok = std::fwrite(hdr, sizeof(int64_t), f->period == N ? 4 : 5, fp) == size_t(f->period == N ? 4 : 5);
     const float* srcs[3] = {f->prm, f->am, f->av};
     for (int k = 0; ok && k < (f->training ? 3 : 1); ++k) {
         if (hipMemcpyAsync(h.data(), srcs[k], NPARAMS * sizeof(float), hipMemcpyDeviceToHost, f->st) != hipSuccess ||
@@ -1969,10 +2001,15 @@ tf_status tf_fno_load(tf_fno* f, const char* path) {
     FILE* fp = std::fopen(path, "rb");
     if (!fp) return fail(TF_EINVAL, std::string("cannot open ") + path);
     int64_t hdr[4];
-    if (std::fread(hdr, sizeof(hdr), 1, fp) != 1 || hdr[0] != 0x4f4e4646554354LL || hdr[1] != 1 ||
+    if (std::fread(hdr, sizeof(hdr), 1, fp) != 1 || hdr[0] != 0x4f4e4646554354LL || (hdr[1] != 1 && hdr[1] != 2) ||
         hdr[2] != NPARAMS) {
         std::fclose(fp);
         return fail(TF_EINVAL, "not a surrogate checkpoint of this architecture");
+    }
+    int64_t period = N;
+    if (hdr[1] == 2 && (std::fread(&period, sizeof(period), 1, fp) != 1 || period < N || period > 4 * N)) {
+        std::fclose(fp);
+        return fail(TF_EINVAL, "bad period in the surrogate checkpoint");
     }
     std::vector<float> h(NPARAMS);
     float* dsts[3] = {f->prm, f->am, f->av};
@@ -1990,6 +2027,10 @@ tf_status tf_fno_load(tf_fno* f, const char* path) {
         }
     }
     std::fclose(fp);
+    if (period != f->period) {
+        tf_status st = upload_tables(f, int(period));
+        if (st != TF_OK) return st;
+    }
     if (f->training) {
         if (nk == 1) {
             TF_HIP(hipMemsetAsync(f->am, 0, NPARAMS * sizeof(float), f->st));

@@ -60,10 +60,14 @@ class tf_window(ctypes.Structure):
                 ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("cz", ctypes.c_double)]
 
 
+TRAIN_PROGRESS = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p)
+
+
 class tf_train_cfg(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
                 ("lr_min_frac", ctypes.c_double), ("seed", ctypes.c_uint64), ("scale_targets", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("epoch_loss", ctypes.POINTER(ctypes.c_double))]
+                ("reserved", ctypes.c_int32), ("epoch_loss", ctypes.POINTER(ctypes.c_double)),
+                ("progress", TRAIN_PROGRESS), ("progress_user", ctypes.c_void_p)]
 
 
 _P = ctypes.c_void_p
@@ -125,6 +129,8 @@ _SIGS = {
     "tf_fno_spectral_forward": ([_P, _P, ctypes.c_int32, _P], ctypes.c_int),
     "tf_fno_spectral_inverse": ([_P, _P, ctypes.c_int32, _P], ctypes.c_int),
     "tf_fno_save": ([_P, ctypes.c_char_p], ctypes.c_int),
+    "tf_fno_set_period": ([_P, ctypes.c_int32], ctypes.c_int),
+    "tf_fno_get_period": ([_P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "tf_fno_load": ([_P, ctypes.c_char_p], ctypes.c_int),
 }
 
@@ -596,7 +602,7 @@ class Surrogate:
     params, head weights, targets and outputs are contiguous float32 CUDA
     tensors."""
 
-    def __init__(self, max_batch, training=False, nbasis=1, stream=None):
+    def __init__(self, max_batch, training=False, nbasis=1, stream=None, period=FNO_N):
         h = ctypes.c_void_p()
         _check(load().tf_fno_create(int(max_batch), 1 if training else 0, int(nbasis), _stream_ptr(stream),
                                     ctypes.byref(h)))
@@ -605,6 +611,18 @@ class Surrogate:
         self.training = bool(training)
         self.nbasis = int(nbasis)
         self.nparams = int(load().tf_fno_param_count(self.nbasis))
+        if period != FNO_N:
+            self.set_period(period)
+
+    def set_period(self, period):
+        """Period of the spectral transform (64: plain; > 64: zero-padded)."""
+        _check(load().tf_fno_set_period(self.h, int(period)))
+
+    @property
+    def period(self):
+        p = ctypes.c_int32()
+        _check(load().tf_fno_get_period(self.h, ctypes.byref(p)))
+        return p.value
 
     def close(self):
         if self.h is not None and self.h.value:
@@ -684,9 +702,11 @@ class Surrogate:
                                          ctypes.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
 
-    def train(self, p, target, epochs, batch, lr, w=None, lr_min_frac=0.02, seed=0, scale_targets=True):
+    def train(self, p, target, epochs, batch, lr, w=None, lr_min_frac=0.02, seed=0, scale_targets=True,
+              progress=None):
         """tf_fno_train over n samples (device tensors p [n, 8], w [n, K],
-        target [n, 6, 64, 64, 64]); returns the per-epoch mean losses."""
+        target [n, 6, 64, 64, 64]); returns the per-epoch mean losses.
+        progress(epoch, loss), if given, is called after every epoch."""
         import numpy as np
         n = p.shape[0]
         pp = self._dev(p, (n, FNO_NPARAM), "params")
@@ -695,8 +715,10 @@ class Surrogate:
         if self.nbasis != 1:
             pw = self._dev(w, (n, self.nbasis), "head weights")
         hist = np.zeros(int(epochs), dtype=np.float64)
+        cb = TRAIN_PROGRESS(lambda ep, loss, _u: progress(int(ep), float(loss))) if progress else TRAIN_PROGRESS()
         cfg = tf_train_cfg(int(epochs), int(batch), float(lr), float(lr_min_frac), int(seed),
-                           1 if scale_targets else 0, 0, hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                           1 if scale_targets else 0, 0, hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                           cb, None)
         last = ctypes.c_double()
         _check(load().tf_fno_train(self.h, pp, pw, pt, int(n), ctypes.byref(cfg), ctypes.byref(last)))
         return hist

@@ -84,30 +84,36 @@ def modes_from_oracle(Xh):
     return np.ascontiguousarray(np.stack([z.real, z.imag], axis=2), dtype=np.float32)
 
 
-def test_truncated_transforms_match_oracle():
+@pytest.mark.parametrize("period", [64, 80, 96])
+def test_truncated_transforms_match_oracle(period):
+    """The truncated DFTs of the spectral branch, plain (period 64) and on
+    the window extended by zeros to a longer period, against the oracle's
+    rfftn / irfftn."""
+    hp = fno.HP(period=period)
     rng = np.random.default_rng(11)
     B = 2
     v = rng.standard_normal((B, 64, 64, 64, HP.width)).astype(np.float32)
-    with tf.Surrogate(B) as s:
+    with tf.Surrogate(B, period=period) as s:
+        assert s.period == period
         vd = torch.from_numpy(v).cuda()
         md = torch.zeros((B, 24, 2, 24, 12, HP.width), dtype=torch.float32, device="cuda")
         s.spectral_forward(vd, md)
         got = modes_to_oracle(md.cpu().numpy().astype(np.float64))
-        ref = fno.spectral_forward(v.astype(np.float64).transpose(0, 4, 1, 2, 3), HP)
+        ref = fno.spectral_forward(v.astype(np.float64).transpose(0, 4, 1, 2, 3), hp)
         assert rel(got, ref) <= SPECTRAL_TOL
         Xh = (rng.standard_normal(ref.shape) + 1j * rng.standard_normal(ref.shape)) * 100.0
         mi = torch.from_numpy(modes_from_oracle(Xh)).cuda()
         ud = torch.zeros((B, 64, 64, 64, HP.width), dtype=torch.float32, device="cuda")
         s.spectral_inverse(mi, ud)
         got_u = ud.cpu().numpy().astype(np.float64).transpose(0, 4, 1, 2, 3)
-        ref_u = fno.spectral_inverse(modes_to_oracle(mi.cpu().numpy().astype(np.float64)), HP)
+        ref_u = fno.spectral_inverse(modes_to_oracle(mi.cpu().numpy().astype(np.float64)), hp)
         assert rel(got_u, ref_u) <= SPECTRAL_TOL
 
 
-def run_forward(P, pb, w=None):
+def run_forward(P, pb, w=None, period=64):
     B = pb.shape[0]
     nb = 1 if w is None else w.shape[1]
-    with tf.Surrogate(B, nbasis=nb) as s:
+    with tf.Surrogate(B, nbasis=nb, period=period) as s:
         s.set_params(P)
         pd = torch.from_numpy(pb.astype(np.float32)).cuda()
         wd = None if w is None else torch.from_numpy(w.astype(np.float32)).cuda()
@@ -157,6 +163,45 @@ def head_weights(rng, B, nb):
     rows = configs.c5_params(B, seed=int(rng.integers(1 << 30)))
     w = np.array([tf.tf_fno_phasor_weights(configs.c5_pulse(r), nb) for r in rows])
     return w.astype(np.float32).astype(np.float64)
+
+
+def test_padded_transform_forward_gradients_and_checkpoint_match_oracle(tmp_path):
+    """Period 80 (the window extended by zeros by 16 nodes per axis) with
+    the four-basis head: forward and every parameter group's gradient
+    against the oracle at the same gates as the plain transform, and a
+    checkpoint that carries the period into a fresh surrogate."""
+    hp = fno.HP(nbasis=4, period=80)
+    P = make_params(41, hp=hp)
+    rng = np.random.default_rng(42)
+    pb = rng.uniform(size=(2, 8)).astype(np.float32).astype(np.float64)
+    w = head_weights(rng, 2, 4)
+    got = run_forward(P, pb, w, period=80)
+    ref = fno.forward(P, pb, hp, w=w)
+    for b in range(2):
+        assert rel(got[b], ref[b]) <= FORWARD_TOL, b
+    assert rel(got, fno.forward(P, pb, fno.HP(nbasis=4), w=w)) > 10 * FORWARD_TOL   # the period matters
+    y = (fno.forward(make_params(43, hp=hp), pb, hp, w=w) + 0.1 * rng.standard_normal((2, 6, 64, 64, 64)))
+    y = y.astype(np.float32)
+    L_ref, G_ref = fno.loss_and_grad(P, pb, y.astype(np.float64), hp, w=w)
+    wd = torch.from_numpy(w.astype(np.float32)).cuda()
+    pd = torch.from_numpy(pb.astype(np.float32)).cuda()
+    with tf.Surrogate(2, training=True, nbasis=4, period=80) as s:
+        s.set_params(P)
+        L, g = s.loss_grad(pd, torch.from_numpy(y).cuda(), wd)
+        path = tmp_path / "padded.ckpt"
+        s.save(path)
+    assert L == pytest.approx(L_ref, rel=FORWARD_TOL)
+    G = tf.fno_unflatten(g)
+    for k, r in G_ref.items():
+        e = rel(G[k], r)
+        cos = float(np.real(np.vdot(G[k].ravel(), r.ravel())) / (np.linalg.norm(G[k]) * np.linalg.norm(r)))
+        assert e <= GRAD_TOL and cos >= GRAD_COS, (k, e, cos)
+    with tf.Surrogate(2, nbasis=4) as s2:
+        s2.load_checkpoint(path)
+        assert s2.period == 80
+        out = torch.zeros((2, 6, 64, 64, 64), dtype=torch.float32, device="cuda")
+        s2.forward(pd, out, wd)
+    assert np.array_equal(out.cpu().numpy(), got.astype(np.float32))
 
 
 def test_four_basis_head_forward_matches_oracle():

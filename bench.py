@@ -157,10 +157,12 @@ def cpu_baseline(start, cfg, focus_step, window_gpu, t_focus, mid=256, single=12
     return base, parity
 
 
-# surrogate training report whose held-out error the bench quotes (written by
-# python -m paper_2010_00409_amd.surrogate on MI355X; the weights themselves
-# are not kept, and inference time does not depend on their values)
-SURROGATE_REPORTS = ("surrogate_k4_head_4000x230_batch4.json",)
+# surrogate training reports whose held-out error the bench quotes, first
+# found wins (written by python -m paper_2010_00409_amd.surrogate on MI355X;
+# the weights themselves are not kept, and inference time does not depend on
+# their values): the spectral path on an 80-periodic zero-padded domain, then
+# the plain 64-periodic one
+SURROGATE_REPORTS = ("surrogate_k4_head_p80_4000x370_batch16.json", "surrogate_k4_head_4000x230_batch4.json")
 
 
 def surrogate_inference_bytes(batch):
@@ -187,7 +189,15 @@ def surrogate_section(reps=20, batch=64):
     from paper_2010_00409_amd import tfocus as tf
     from synthetic import configs
 
-    sur = tf.Surrogate(batch, nbasis=4)
+    rep, src = None, None
+    for name in SURROGATE_REPORTS:
+        path = os.path.join(HERE, "profiles", name)
+        if os.path.exists(path):
+            rep, src = json.load(open(path)), "profiles/" + name
+            break
+    err = rep["test_rel_l2"] if rep else None
+    period = rep.get("period", 64) if rep else 64
+    sur = tf.Surrogate(batch, nbasis=4, period=period)
     sur.set_params(sg.init_params(0, 4))
     t_b = sg.time_surrogate(sur, batch, reps=reps)
     t_1 = sg.time_surrogate(sur, 1, reps=reps)
@@ -196,23 +206,17 @@ def surrogate_section(reps=20, batch=64):
     t_sol1, t_solb = sg.time_solver(pulse, reps=3, batch=batch)
     alg = surrogate_inference_bytes(batch)
     achieved = alg / (t_b * batch) / 1e9
-    rep, src = None, None
-    for name in SURROGATE_REPORTS:
-        path = os.path.join(HERE, "profiles", name)
-        if os.path.exists(path):
-            rep, src = json.load(open(path)), "profiles/" + name
-            break
-    err = rep["test_rel_l2"] if rep else None
     return {
         "s_per_window": {"batch1": t_1, f"batch{batch}": t_b},
         "solver_s_per_window": {"single": t_sol1, f"batch{batch}": t_solb},
         "speedup": {"batch1_vs_single": t_sol1 / t_1, f"batch{batch}": t_solb / t_b},
-        "heldout_rel_l2": err, "heldout_source": src,
+        "heldout_rel_l2": err, "heldout_source": src, "spectral_period": period,
         "meets_1e-2": (err["mean"] <= 1e-2) if err else None,
         "roofline": {"bound": "hbm", "kernel": "fused inference pass", "achieved": achieved,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "alg_bytes_per_launch": alg},
-        "workload": ("C5: 3-layer FNO (width 32, 12 modes/axis, four-basis head) -> 6 x 64^3 focal window; "
+        "workload": (f"C5: 3-layer FNO (width 32, 12 modes/axis of a {period}-periodic transform, four-basis head) "
+                     "-> 6 x 64^3 focal window; "
                      "solver: 96x256x256 layer, dx = lambda/12, one exact step to t = R0, cut-out"),
     }
 

@@ -284,6 +284,11 @@ inline StepParams step_params(const tf_grid& g, double dt, bool project_b, int z
     p.scale = 1.0 / ((double)g.nx * (double)g.ny * (double)g.nz);
     p.project_b = project_b ? 1 : 0;
     p.zvariant = zvariant;
+    // largest phase c |k| dt of the grid (signed modes reach n/2 per axis);
+    // up to 8 rad z variant 10 builds its phase factors in float32
+    const double kmax = std::sqrt(std::pow(p.kfx * (g.nx / 2), 2) + std::pow(p.kfy * (g.ny / 2), 2) +
+                                  std::pow(p.kfz * (g.nz / 2), 2));
+    p.phase32 = std::fabs(p.cdt) * kmax <= 8.0 ? 1 : 0;
     return p;
 }
 
@@ -331,6 +336,7 @@ hipError_t step_passes(void* state, void* spec, void* const* tw, const tf_grid& 
     e = launch_y_pass<T>(spec, tw[1], g.nx, g.ny, g.nz, -1, rm, kp.yarg(), bt, st);
     if (e != hipSuccess) return e;
     StepParams p = step_params(g, dt, project_b, kp.zvariant);
+    if (bt.cdt) p.phase32 = 0;          // per-instance time steps: the phase bound is not known here
     e = launch_z_pass<T>(spec, tw[2], p, rm, Z_STEP, nullptr, nullptr, nullptr, kp.fast, bt, st);
     if (e != hipSuccess) return e;
     e = launch_y_pass<T>(spec, tw[1], g.nx, g.ny, g.nz, +1, rm, kp.yarg(), bt, st);

@@ -55,6 +55,7 @@ struct StepParams {
     double scale;            // 1 / (nx ny nz)
     int project_b;           // also remove the longitudinal part of B
     int zvariant;            // shape of the fused float32 z kernel (strip modes, elements per lane, first radix)
+    int phase32;             // |c dt| |k|max <= 8: z variant 10 may build the phase in float32
 };
 
 enum ZMode { Z_STEP = 0, Z_DIAG = 1, Z_STEP_DIAG = 2 };

@@ -1,6 +1,8 @@
 """GPU parity: the HIP path through the C ABI against the float64 oracle on
 the same seeded inputs.  Tolerances (relative L2 over all six components):
 float64 <= 1e-12, float32 <= 1e-5 per step."""
+import math
+
 import numpy as np
 import pytest
 
@@ -319,7 +321,7 @@ def test_graph_replayed_steps_equal_eager_steps_bitwise(prec):
     assert rel(outs[1][0].astype(np.float64), np.concatenate([Eo, Bo])) <= tol
 
 
-@pytest.mark.parametrize("zvariant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9])
+@pytest.mark.parametrize("zvariant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
 def test_every_z_variant_at_length_512(zvariant, monkeypatch):
     """512-point z columns (where variants 5 and 6 differ, residues are
     parked in LDS or held in registers, and variants 7 and 8 run one wave per
@@ -332,7 +334,26 @@ def test_every_z_variant_at_length_512(zvariant, monkeypatch):
     assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= 2 * F32_TOL
 
 
-@pytest.mark.parametrize("zvariant", [7, 8, 9])
+@pytest.mark.parametrize("zvariant", [7, 9, 10])
+def test_long_run_of_512_point_z_kernels_matches_oracle_jump(zvariant, monkeypatch):
+    """300 float32 steps with phases c |k| dt up to 7.8 rad per step (where
+    variant 10 builds the phase in float32) against the oracle's single exact
+    jump (Sec. II.A).  A phase that errs the same way on every step would grow
+    linearly with the step count; float32 rounding of the transforms grows as
+    a random walk, and the gate is sqrt(steps) times the one-step tolerance."""
+    monkeypatch.setenv("TFOCUS_ZVARIANT", str(zvariant))
+    g, st = transverse_state(71, (512, 8, 16), 0.3)
+    st = st.astype(np.float32).astype(np.float64)
+    steps, dt = 300, 0.43
+    out, t = run_gpu(g, "f32", st, steps, dt)
+    Eo, Bo = psatd.jump(st[:3], st[3:], spacing(g), steps * dt)
+    e = rel(out.astype(np.float64), np.concatenate([Eo, Bo]))
+    print(f"z variant {zvariant}: {steps} steps vs jump {e:.2e}")
+    assert t == pytest.approx(steps * dt)
+    assert e <= math.sqrt(steps) * F32_TOL
+
+
+@pytest.mark.parametrize("zvariant", [7, 8, 9, 10])
 def test_wave_z_kernel_projection_and_huge_phases(zvariant, monkeypatch):
     """The one-wave-per-mode z kernel on 512-point columns: the first step
     after tf_set_pulse (which also removes longitudinal B) against the

@@ -442,3 +442,18 @@ def test_every_kernel_plan_keeps_parity(n, zvariant, row_block, monkeypatch):
     out, _ = run_gpu(g, "f32", st, 2, 0.41)
     Eo, Bo = psatd.step_fft(st[:3], st[3:], spacing(g), 0.41, nsteps=2)
     assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= 2 * F32_TOL
+
+
+@pytest.mark.parametrize("n,row_block", [(128, 16), (192, 64), (256, 32)])
+def test_row_blocks_wider_than_the_y_kernel_steps(n, row_block, monkeypatch):
+    """Row blocks that do not divide the fast y kernel's row steps, where it
+    looks every row up instead of stepping linearly (and the z kernels read
+    the wider blocks)."""
+    monkeypatch.setenv("TFOCUS_ROW_BLOCK", str(row_block))
+    plan = tf.tf_kernel_plan(dict(nx=n, ny=n, nz=n, dx=0.3, dy=0.3, dz=0.3, x_min=0.0, y_min=0.0, z_min=0.0), "f32")
+    assert plan[0] == row_block and plan[1]
+    g, st = transverse_state(n + row_block, (n, n, n), 0.3)
+    st = st.astype(np.float32).astype(np.float64)
+    out, _ = run_gpu(g, "f32", st, 2, 0.41)
+    Eo, Bo = psatd.step_fft(st[:3], st[3:], spacing(g), 0.41, nsteps=2)
+    assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= 2 * F32_TOL

@@ -64,19 +64,33 @@ template <typename T, int DIR> __device__ __forceinline__ void dft4(C2<T>* v) {
     v[1] = cadd(t1, t3); v[3] = csub(t1, t3);
 }
 
+// a + s b, elementwise with fused multiply-adds
+template <typename V, typename S> __device__ __forceinline__ V cfma(S s, V b, V a) {
+    a.x = fma(s, b.x, a.x); a.y = fma(s, b.y, a.y); return a;
+}
+
+// Radix 2 x 4: even outputs are the 4-point DFT of c_k = v_k + v_(k+4); odd
+// outputs the 4-point DFT of (v_k - v_(k+4)) w8^k, w8 = exp(DIR 2 pi i / 8).
+// w8 and w8^3 are sqrt(2)/2 (1 + DIR i) and sqrt(2)/2 (-1 + DIR i); the
+// common factor sqrt(2)/2 is applied in the last additions as fused
+// multiply-adds.
 template <typename T, int DIR> __device__ __forceinline__ void dft8(C2<T>* v) {
     C2<T> b[4], c[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) { b[k] = cadd(v[k], v[k + 4]); c[k] = csub(v[k], v[k + 4]); }
-    // c_k *= w8^k, w8 = exp(DIR 2 pi i / 8)
     const T s = Consts<T>::r2;
-    { C2<T> d = c[1]; C2<T> id = cmul_i<DIR>(d); c[1].x = s * (d.x + id.x); c[1].y = s * (d.y + id.y); }
-    c[2] = cmul_i<DIR>(c[2]);
-    { C2<T> d = c[3]; C2<T> id = cmul_i<DIR>(d); c[3].x = s * (id.x - d.x); c[3].y = s * (id.y - d.y); }
+    const C2<T> u1 = cadd(c[1], cmul_i<DIR>(c[1]));            // c1 w8 / s
+    const C2<T> u3 = csub(cmul_i<DIR>(c[3]), c[3]);            // c3 w8^3 / s
+    const C2<T> c2 = cmul_i<DIR>(c[2]);                        // c2 w8^2
+    const C2<T> t0 = cadd(c[0], c2), t1 = csub(c[0], c2);
+    const C2<T> pa = cadd(u1, u3), pb = cmul_i<DIR>(csub(u1, u3));
     dft4<T, DIR>(b);
-    dft4<T, DIR>(c);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) { v[2 * m] = b[m]; v[2 * m + 1] = c[m]; }
+    for (int m = 0; m < 4; ++m) v[2 * m] = b[m];
+    v[1] = cfma(s, pa, t0);
+    v[5] = cfma(-s, pa, t0);
+    v[3] = cfma(s, pb, t1);
+    v[7] = cfma(-s, pb, t1);
 }
 
 // cos and sin of 2 pi k / R for odd R = 5, 7 and k = 1 .. (R - 1) / 2

@@ -46,7 +46,8 @@ def pass_kernels(plan, nz):
     if not fast:
         z, col = "k_z", "k_col"
     else:
-        z, col = ("k_z_wave" if zv >= 7 and nz == 512 else "k_z_fast"), "k_col_fast"
+        waves = {512: "k_z_wave", 256: "k_z_wave256"}
+        z, col = (waves[nz] if zv >= 7 and nz in waves else "k_z_fast"), "k_col_fast"
     return {"x_forward": "k_x_forward", "y_forward": col, "z_step": z, "y_inverse": col,
             "x_inverse": "k_x_inverse"}
 

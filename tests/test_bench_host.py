@@ -80,7 +80,9 @@ def test_traffic_record_needs_the_current_kernel_sources(tmp_path, monkeypatch):
 def test_pass_kernels_follow_the_plan():
     assert bench.pass_kernels((8, True, 7), 512)["z_step"] == "k_z_wave"
     assert bench.pass_kernels((8, True, 8), 512)["z_step"] == "k_z_wave"
-    assert bench.pass_kernels((8, True, 7), 256)["z_step"] == "k_z_fast"
+    assert bench.pass_kernels((8, True, 7), 256)["z_step"] == "k_z_wave256"
+    assert bench.pass_kernels((8, True, 7), 128)["z_step"] == "k_z_fast"
+    assert bench.pass_kernels((8, True, 4), 256)["z_step"] == "k_z_fast"
     assert bench.pass_kernels((8, True, 6), 512)["z_step"] == "k_z_fast"
     k = bench.pass_kernels((8, False, 0), 512)
     assert (k["z_step"], k["y_forward"], k["x_inverse"]) == ("k_z", "k_col", "k_x_inverse")

@@ -430,7 +430,7 @@ def test_determinism_bitwise():
 
 
 @pytest.mark.parametrize("n", [64, 128, 192, 256])
-@pytest.mark.parametrize("zvariant", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("zvariant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("row_block", ["8", "n"])
 def test_every_kernel_plan_keeps_parity(n, zvariant, row_block, monkeypatch):
     """Each z strip shape and y row blocking the tuner can pick."""
@@ -457,3 +457,24 @@ def test_row_blocks_wider_than_the_y_kernel_steps(n, row_block, monkeypatch):
     out, _ = run_gpu(g, "f32", st, 2, 0.41)
     Eo, Bo = psatd.step_fft(st[:3], st[3:], spacing(g), 0.41, nsteps=2)
     assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= 2 * F32_TOL
+
+
+@pytest.mark.parametrize("zvariant", [7, 8])
+def test_wave_z_kernel_at_length_256_long_run_and_huge_phases(zvariant, monkeypatch):
+    """The one-wave-per-mode z kernel on 256-point columns (radix 4, then the
+    64-point lane transform over component pairs): 300 float32 steps against
+    the oracle's single exact jump (Sec. II.A), and one step with phases
+    c |k| dt up to 1e5 rad on fields with a longitudinal part."""
+    monkeypatch.setenv("TFOCUS_ZVARIANT", str(zvariant))
+    g, st = transverse_state(130 + zvariant, (256, 16, 32), 0.3)
+    st = st.astype(np.float32).astype(np.float64)
+    steps, dt = 300, 0.43
+    out, _ = run_gpu(g, "f32", st, steps, dt)
+    Eo, Bo = psatd.jump(st[:3], st[3:], spacing(g), steps * dt)
+    e = rel(out.astype(np.float64), np.concatenate([Eo, Bo]))
+    print(f"z variant {zvariant} at 256: {steps} steps vs jump {e:.2e}")
+    assert e <= math.sqrt(steps) * F32_TOL
+    y = np.random.default_rng(zvariant).standard_normal((6, 256, 16, 32)).astype(np.float32)
+    out2, _ = run_gpu(g, "f32", y, 1, 1.0e4)
+    Eo, Bo = psatd.step_fft(y[:3].astype(np.float64), y[3:].astype(np.float64), spacing(g), 1.0e4)
+    assert rel(out2.astype(np.float64), np.concatenate([Eo, Bo])) <= F32_TOL

@@ -407,4 +407,23 @@ __device__ __forceinline__ void load_twiddles(C2<T>* dst, const C2<T>* __restric
     for (int e = tid; e < N; e += NT) dst[e] = src[e];
 }
 
+// The same copy in two halves: fetch() requests a thread's table entries into
+// registers and store() writes them to LDS, so that a kernel can request its
+// data rows in between and wait for the table alone (memory requests
+// complete in order) instead of for a round trip before its first row.
+template <typename T, int N, int NT> struct TwiddleCopy {
+    static constexpr int K = (N + NT - 1) / NT;
+    C2<T> r[K];
+    __device__ __forceinline__ void fetch(const C2<T>* __restrict__ src, int tid) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (tid + k * NT < N) r[k] = src[tid + k * NT];
+    }
+    __device__ __forceinline__ void store(C2<T>* dst, int tid) const {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (tid + k * NT < N) dst[tid + k * NT] = r[k];
+    }
+};
+
 }  // namespace tf

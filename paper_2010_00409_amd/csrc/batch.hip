@@ -550,14 +550,15 @@ tf_status tf_tune(const int32_t* sizes, int32_t n, int32_t precision, const char
             p.fast = false;
             cands.push_back(p);
             if (!fast_offsets_fit(g, rb, precision)) continue;
-            // variants 7 to 9 (one wave per mode) exist for 512-point z
-            // columns, 7 and 8 for 256-point ones; elsewhere they run
-            // variant 6.  Variant 10 (float32
+            // variants 7 to 9 and 11 (one wave per mode) exist for
+            // 512-point z columns, 7 and 8 for 256-point ones; elsewhere
+            // they run variant 6.  Variant 10 (float32
             // phases) is left to explicit plans: its phase error is the same
             // on every step, so it grows linearly with the step count, for
             // about 1% of the z pass's time
             for (int ys : {64, 32})
-                for (int zv = 0; zv < (N == 512 ? 10 : N == 256 ? 9 : 7); ++zv) {
+                for (int zv = 0; zv < (N == 512 ? 12 : N == 256 ? 9 : 7); ++zv) {
+                    if (zv == 10) continue;
                     p.fast = true;
                     p.zvariant = zv;
                     p.ystrip = ys;

@@ -321,7 +321,7 @@ def test_graph_replayed_steps_equal_eager_steps_bitwise(prec):
     assert rel(outs[1][0].astype(np.float64), np.concatenate([Eo, Bo])) <= tol
 
 
-@pytest.mark.parametrize("zvariant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
+@pytest.mark.parametrize("zvariant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
 def test_every_z_variant_at_length_512(zvariant, monkeypatch):
     """512-point z columns (where variants 5 and 6 differ, residues are
     parked in LDS or held in registers, and variants 7 and 8 run one wave per
@@ -334,7 +334,7 @@ def test_every_z_variant_at_length_512(zvariant, monkeypatch):
     assert rel(out.astype(np.float64), np.concatenate([Eo, Bo])) <= 2 * F32_TOL
 
 
-@pytest.mark.parametrize("zvariant", [7, 9, 10])
+@pytest.mark.parametrize("zvariant", [7, 9, 10, 11])
 def test_long_run_of_512_point_z_kernels_matches_oracle_jump(zvariant, monkeypatch):
     """300 float32 steps with phases c |k| dt up to 7.8 rad per step (where
     variant 10 builds the phase in float32) against the oracle's single exact
@@ -353,7 +353,7 @@ def test_long_run_of_512_point_z_kernels_matches_oracle_jump(zvariant, monkeypat
     assert e <= math.sqrt(steps) * F32_TOL
 
 
-@pytest.mark.parametrize("zvariant", [7, 8, 9, 10])
+@pytest.mark.parametrize("zvariant", [7, 8, 9, 10, 11])
 def test_wave_z_kernel_projection_and_huge_phases(zvariant, monkeypatch):
     """The one-wave-per-mode z kernel on 512-point columns: the first step
     after tf_set_pulse (which also removes longitudinal B) against the

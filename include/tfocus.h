@@ -356,10 +356,11 @@ tf_status tf_kernel_plan(const tf_grid* grid, int32_t precision, int32_t* row_bl
 
 /* For each cube size N in sizes[0..n): time a few steps of every kernel
  * plan (y row blocking 8 or none; generic kernels or the fast float32
- * kernels with each z strip shape) on the current device with HIP events,
- * on pseudo-random fields, in three interleaved rounds (each plan keeps its
- * fastest round); keep the fastest plan and merge "arch precision N N N
- * row_block fast zvariant ms" into plan_path.  best_ms (nullable) receives
+ * kernels with each z strip shape of that length and both y strip widths)
+ * on the current device with HIP events, on pseudo-random fields, in three
+ * interleaved rounds (each plan keeps its fastest round); keep the fastest
+ * plan and merge "arch precision N N N row_block fast zvariant ystrip ms"
+ * into plan_path.  best_ms (nullable) receives
  * the best ms per step.  Allocates two N^3 six-component states on the
  * current device for the duration of the call. */
 tf_status tf_tune(const int32_t* sizes, int32_t n, int32_t precision, const char* plan_path, double* best_ms);

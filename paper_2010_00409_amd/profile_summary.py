@@ -145,10 +145,13 @@ def kernel_sources(unit="fft_f32.hip"):
 
 
 def source_hash():
-    """SHA-256 of the pass kernels' sources: counters recorded against it
-    stay valid while those kernels are unchanged."""
+    """SHA-256 of the pass kernels' sources and their build flags (the float32
+    translation units, the headers they include and build.py): counters
+    recorded against it stay valid while those kernels are unchanged."""
     h = hashlib.sha256()
-    for path in kernel_sources():
+    paths = kernel_sources() + [p for p in kernel_sources("fft_f32_zwave.hip") if p not in kernel_sources()]
+    paths.append(os.path.join(os.path.dirname(os.path.abspath(__file__)), "build.py"))
+    for path in paths:
         h.update(open(path, "rb").read())
     return h.hexdigest()
 

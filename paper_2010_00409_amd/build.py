@@ -21,7 +21,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(HERE, "..", "include"), "-Wno-unused-command-line-argument"]
 PER_FILE = {"field_kernels.hip": ["-ffp-contract=off"],
-            # the 512-point z wave kernel of the shipped plan: memory-clause scheduling
+            # the z wave kernels of the shipped plans: memory-clause scheduling
             "fft_f32_zwave.hip": ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"]}
 
 

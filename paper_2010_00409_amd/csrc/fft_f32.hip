@@ -5,6 +5,8 @@ namespace tf {
 // compiled in fft_f32_zwave.hip with its own scheduling strategy
 extern template __global__ void k_z_wave<4, 1, false, 2>(float2* __restrict__, const float2* __restrict__, StepParams,
                                                          RowMap, Batch);
+extern template __global__ void k_z_wave256<4, 3>(float2* __restrict__, const float2* __restrict__, StepParams, RowMap,
+                                                  Batch);
 template hipError_t launch_x_forward<float>(const float*, void*, const void*, int, int, int, RowMap, Batch, hipStream_t);
 template hipError_t launch_x_inverse<float>(const void*, float*, const void*, int, int, int, RowMap, Batch, hipStream_t);
 template hipError_t launch_y_pass<float>(void*, const void*, int, int, int, int, RowMap, int, Batch, hipStream_t);
